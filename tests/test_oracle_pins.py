@@ -1,0 +1,411 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test ties the oracle to something other than itself: a closed form, an
+invariant of Eq. 1-2, a textbook special case computed by a library routine,
+an exact error bound, finite differences, or a pure-Python brute force on a
+tiny input.  A plausible mistake (dropped term, wrong sign, wrong index,
+transposed operand, wrong radius predicate) fails at least one of them.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2012_13257_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _sigmoid(t):
+    return 1.0 / (1.0 + math.exp(-t))
+
+
+# --------------------------------------------------------------------------
+# Forward pins
+# --------------------------------------------------------------------------
+
+def test_two_point_sigmoid_closed_form():
+    """Two points on a line at x=a and x=a+1 (equal sigma, same row offset):
+    the mean is c0 + (c1-c0) * sigmoid((2(u-a)-1) / (2 sigma^2)) (Eq. 1 with N=2)."""
+    with open(os.path.join(GOLDEN, "two_point_sigmoid.json")) as f:
+        g = json.load(f)
+    a, s, y0 = g["a"], g["sigma"], g["y"]
+    c0, c1 = np.array(g["c0"]), np.array(g["c1"])
+    W = len(g["u"])
+    pos = np.array([[[a, y0], [a + 1.0, y0]]], dtype=np.float64)
+    val = np.array([[c0, c1]], dtype=np.float64)
+    sig = np.array([[s, s]], dtype=np.float64)
+    r = oracle.forward(pos, sig, val, 1, W, radius=None)
+    for u in range(W):
+        expect = np.array(g["out"][u])
+        np.testing.assert_allclose(r["out"][0, :, 0, u], expect, rtol=1e-13, atol=1e-15)
+        # the table itself is the closed form (independent of the oracle)
+        t = (2 * (u - a) - 1) / (2 * s * s)
+        np.testing.assert_allclose(expect, c0 + (c1 - c0) * _sigmoid(t), rtol=1e-14)
+
+
+def test_single_point_gives_own_value_inside_radius_zero_outside():
+    rng = np.random.default_rng(3)
+    H, W = 11, 13
+    x, y, s = 6.3, 4.7, 1.1
+    c = rng.random(4)
+    pos = np.array([[[x, y]]], np.float32)
+    r = oracle.forward(pos, np.array([s], np.float32), c[None, None].astype(np.float32), H, W, 3.0)
+    rs = np.float32(3.0) * np.float32(s)
+    for v in range(H):
+        for u in range(W):
+            inside = (u - x) ** 2 + (v - y) ** 2 <= float(rs) ** 2 * (1 - 1e-6)
+            outside = (u - x) ** 2 + (v - y) ** 2 >= float(rs) ** 2 * (1 + 1e-6)
+            if inside:
+                np.testing.assert_allclose(r["out"][0, :, v, u], c.astype(np.float32), rtol=1e-15)
+                assert r["Z"][0, v, u] == pytest.approx(
+                    math.exp(-((u - np.float32(x)) ** 2 + (v - np.float32(y)) ** 2) / (2 * np.float32(s) ** 2)))
+            if outside:
+                assert r["Z"][0, v, u] == 0 and np.all(r["out"][0, :, v, u] == 0)
+
+
+def test_uniform_grid_small_sigma_reproduces_nodes_exactly():
+    """One point per pixel node, r*sigma < 1: each pixel only sees its own node, w=1."""
+    H, W = 9, 12
+    vv, uu = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    pos = np.stack([uu.ravel(), vv.ravel()], 1).astype(np.float32)[None]
+    rng = np.random.default_rng(5)
+    val = rng.random((1, H * W, 3)).astype(np.float32)
+    r = oracle.forward(pos, np.array([0.2], np.float32), val, H, W, 3.0)
+    expect = val[0].reshape(H, W, 3).transpose(2, 0, 1)
+    assert np.array_equal(r["out"][0], expect.astype(np.float64))
+    assert np.all(r["Z"] == 1.0)
+    assert r["P"] == H * W
+
+
+def test_constant_colour_is_reproduced():
+    wl = synth.random_workload(11, 1, 300, 20, 24, C=2, sigma=(0.4, 2.5))
+    val = np.full_like(wl.values, 0.375)
+    r = oracle.forward(wl.pos, wl.sigma, val, wl.H, wl.W, 3.0)
+    m = r["Z"][0] > 0
+    assert m.sum() > 100
+    np.testing.assert_allclose(r["out"][0][:, m], 0.375, rtol=1e-14)
+
+
+def test_symmetric_points_give_plain_mean():
+    d = 1.25
+    u0, v0 = 5, 4
+    pos = np.array([[[u0 + d, v0], [u0 - d, v0], [u0, v0 + d], [u0, v0 - d]]], np.float32)
+    val = np.array([[[1.0], [3.0], [7.0], [-2.0]]], np.float32)
+    r = oracle.forward(pos, np.array([0.9], np.float32), val, 10, 10, 3.0)
+    assert r["out"][0, 0, v0, u0] == pytest.approx((1 + 3 + 7 - 2) / 4, rel=1e-14)
+
+
+def test_separable_normalised_convolution_textbook_case():
+    """Uniform unit grid, shared sigma, no truncation: Eq. 1 is Nadaraya-Watson
+    regression = ratio of two separable Gaussian filterings (of c and of 1),
+    computed here with numpy.convolve along rows and then columns."""
+    H, W, s = 10, 14, 1.3
+    rng = np.random.default_rng(9)
+    img = rng.random((H, W))
+    vv, uu = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    pos = np.stack([uu.ravel(), vv.ravel()], 1).astype(np.float64)[None]
+    val = img.reshape(1, H * W, 1)
+    r = oracle.forward(pos, np.array([s]), val, H, W, radius=None)
+
+    def filt(a):
+        L = max(H, W)
+        k = np.exp(-np.arange(-L, L + 1) ** 2 / (2 * s * s))
+        rows = np.stack([np.convolve(a[i], k)[L: L + W] for i in range(H)])
+        return np.stack([np.convolve(rows[:, j], k)[L: L + H] for j in range(W)], axis=1)
+
+    expect = filt(img) / filt(np.ones_like(img))
+    np.testing.assert_allclose(r["out"][0, 0], expect, rtol=1e-12)
+
+
+def test_truncation_tail_bound_exact_and_rayleigh():
+    """|o^r - o^inf| <= (Z_out / Z_inf) (max c - min c) holds exactly; on a dense
+    unit grid with a shared sigma, Z_out/Z_inf is close to exp(-r^2/2)."""
+    H = W = 30
+    s = 2.0
+    vv, uu = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    pos = np.stack([uu.ravel(), vv.ravel()], 1).astype(np.float32)[None]
+    rng = np.random.default_rng(2)
+    val = rng.random((1, H * W, 1)).astype(np.float32)
+    # centre pixels only (the full disk fits inside the grid there)
+    vs, us = np.meshgrid(np.arange(12, 18), np.arange(12, 18), indexing="ij")
+    b = np.zeros(vs.size, np.int64)
+    sig = np.array([s], np.float32)
+    rt = oracle.forward_pixels(pos, sig, val, 3.0, b, vs.ravel(), us.ravel())
+    ri = oracle.forward_pixels(pos, sig, val, None, b, vs.ravel(), us.ravel())
+    frac = (ri["Z"] - rt["Z"]) / ri["Z"]
+    spread = float(val.max() - val.min())
+    assert np.all(np.abs(rt["out"][:, 0] - ri["out"][:, 0]) <= frac * spread + 1e-15)
+    assert np.all(frac > 0)
+    np.testing.assert_allclose(frac, math.exp(-4.5), rtol=0.15)
+
+
+def test_affine_in_values_and_permutation_invariant():
+    wl = synth.random_workload(21, 1, 200, 16, 18, C=3, sigma=(0.5, 2.0))
+    r1 = oracle.forward(wl.pos, wl.sigma, wl.values, wl.H, wl.W, 3.0)
+    a, bshift = -1.75, 0.5
+    r2 = oracle.forward(wl.pos, wl.sigma, (a * wl.values.astype(np.float64) + bshift),
+                        wl.H, wl.W, 3.0)
+    m = r1["Z"][0] > 0
+    np.testing.assert_allclose(r2["out"][0][:, m], a * r1["out"][0][:, m] + bshift, rtol=1e-12)
+    p = np.random.default_rng(0).permutation(wl.N)
+    r3 = oracle.forward(wl.pos[:, p], wl.sigma[:, p], wl.values[:, p], wl.H, wl.W, 3.0)
+    np.testing.assert_allclose(r3["out"], r1["out"], rtol=1e-13, atol=1e-15)
+    assert r3["P"] == r1["P"]
+
+
+def test_integer_translation_shifts_output():
+    """Dyadic positions make u - x exact, so an integer shift of every point
+    shifts every output pixel exactly."""
+    rng = np.random.default_rng(4)
+    N, H, W = 60, 12, 12
+    pos = (np.round(rng.random((1, N, 2)) * 12 * 64) / 64).astype(np.float32)
+    sig = (np.round(rng.uniform(0.5, 1.5, (1, N)) * 64) / 64).astype(np.float32)
+    val = rng.random((1, N, 2)).astype(np.float32)
+    r1 = oracle.forward(pos, sig, val, H, W, 3.0)
+    sh = pos + np.array([3.0, 2.0], np.float32)
+    r2 = oracle.forward(sh, sig, val, H + 2, W + 3, 3.0)
+    np.testing.assert_array_equal(r2["out"][0][:, 2:, 3:], r1["out"][0])
+
+
+def test_pure_python_brute_force_tiny():
+    """Independent scalar loop over the definition on a tiny input."""
+    rng = np.random.default_rng(17)
+    H, W, N, C = 5, 6, 9, 2
+    pos = (rng.random((1, N, 2)) * [W, H]).astype(np.float32)
+    sig = rng.uniform(0.4, 1.6, (1, N)).astype(np.float32)
+    val = rng.standard_normal((1, N, C)).astype(np.float32)
+    r = oracle.forward(pos, sig, val, H, W, 2.5)
+    f32 = np.float32
+    for v in range(H):
+        for u in range(W):
+            num = [0.0] * C
+            absnum = [0.0] * C
+            z = 0.0
+            for j in range(N):
+                x, y, s = pos[0, j, 0], pos[0, j, 1], sig[0, j]
+                dx = f32(f32(u) - x)
+                dy = f32(f32(v) - y)
+                d2 = f32(f32(dx * dx) + f32(dy * dy))
+                rs = f32(f32(2.5) * s)
+                if d2 <= f32(rs * rs):
+                    w = math.exp(-((u - float(x)) ** 2 + (v - float(y)) ** 2) / (2 * float(s) ** 2))
+                    z += w
+                    for k in range(C):
+                        num[k] += w * float(val[0, j, k])
+                        absnum[k] += w * abs(float(val[0, j, k]))
+            for k in range(C):
+                ref = num[k] / z if z > 0 else 0.0
+                assert r["out"][0, k, v, u] == pytest.approx(ref, rel=1e-12, abs=1e-14)
+                sref = absnum[k] / z if z > 0 else 0.0
+                assert r["S"][0, k, v, u] == pytest.approx(sref, rel=1e-12, abs=1e-14)
+            assert r["Z"][0, v, u] == pytest.approx(z, rel=1e-12, abs=0)
+
+
+def test_predicate_near_radius_follows_float32_sequence():
+    """Near |d| = r*sigma the decision depends on float32 rounding; the oracle
+    must follow the specified float32 operation sequence, which differs from a
+    float64 evaluation on some of these cases."""
+    f32 = np.float32
+    differs = 0
+    for s in [0.1, 0.37, 0.5, 0.7, 1.1, 1.3, 1.9, 2.7]:
+        s = f32(s)
+        for r in [2.0, 3.0, 3.5]:
+            rs = f32(f32(r) * s)
+            for k in range(-6, 7):
+                for ang in [(1, 0), (0, 1), (3, 4)]:
+                    dist = float(rs) * (1 + k * 2.0 ** -23)
+                    x = f32(5.0 - dist * ang[0] / math.hypot(*ang))
+                    y = f32(4.0 - dist * ang[1] / math.hypot(*ang))
+                    dx = f32(f32(5.0) - x)
+                    dy = f32(f32(4.0) - y)
+                    d2 = f32(f32(dx * dx) + f32(dy * dy))
+                    ref = bool(d2 <= f32(rs * rs))
+                    assert bool(oracle.predicate(5, 4, x, y, s, r)) == ref
+                    exact = (5.0 - float(x)) ** 2 + (4.0 - float(y)) ** 2 <= (r * float(s)) ** 2
+                    differs += exact != ref
+    assert differs > 0
+
+
+def test_predicate_is_inclusive_and_float32():
+    # point exactly at distance r*sigma along an axis: d2 == R2 exactly -> included
+    assert oracle.predicate(3, 0, 0.0, 0.0, 1.0, 3.0)
+    assert not oracle.predicate(4, 0, 0.0, 0.0, 1.0, 3.0)
+    # float32 rounding of r*sigma decides: r*sigma = 3*0.1 in float32 is 0.3 (rounded up)
+    s = np.float32(0.1)
+    rs = np.float32(3.0) * s
+    x = np.float32(-float(rs))  # |u - x| == rs exactly
+    assert oracle.predicate(0, 0, x, 0.0, s, 3.0)
+    assert not oracle.predicate(0, 0, np.nextafter(x, np.float32(-1)), 0.0, s, 3.0)
+
+
+# --------------------------------------------------------------------------
+# Backward pins
+# --------------------------------------------------------------------------
+
+def _loss(pos, sig, val, G, H, W, radius):
+    r = oracle.forward(pos, sig, val, H, W, radius)
+    return float(np.sum(r["out"] * G))
+
+
+@pytest.mark.parametrize("shared", [False, True])
+def test_backward_matches_central_finite_differences(shared):
+    rng = np.random.default_rng(23 + shared)
+    H, W, N, C = 7, 8, 6, 2
+    pos = rng.random((1, N, 2)) * [W, H]
+    sig = np.array([1.1]) if shared else rng.uniform(0.6, 1.6, (1, N))
+    val = rng.standard_normal((1, N, C))
+    G = rng.standard_normal((1, C, H, W))
+    g = oracle.backward(pos, sig, val, G, H, W, radius=None)
+    h = 1e-6
+    for j in range(N):
+        for d in range(2):
+            p1, p2 = pos.copy(), pos.copy()
+            p1[0, j, d] += h
+            p2[0, j, d] -= h
+            fd = (_loss(p1, sig, val, G, H, W, None) - _loss(p2, sig, val, G, H, W, None)) / (2 * h)
+            assert g["grad_pos"][0, j, d] == pytest.approx(fd, rel=1e-6, abs=1e-8)
+        for k in range(C):
+            v1, v2 = val.copy(), val.copy()
+            v1[0, j, k] += h
+            v2[0, j, k] -= h
+            fd = (_loss(pos, sig, v1, G, H, W, None) - _loss(pos, sig, v2, G, H, W, None)) / (2 * h)
+            assert g["grad_values"][0, j, k] == pytest.approx(fd, rel=1e-6, abs=1e-8)
+        if not shared:
+            s1, s2 = sig.copy(), sig.copy()
+            s1[0, j] += h
+            s2[0, j] -= h
+            fd = (_loss(pos, s1, val, G, H, W, None) - _loss(pos, s2, val, G, H, W, None)) / (2 * h)
+            assert g["grad_sigma"][0, j] == pytest.approx(fd, rel=1e-6, abs=1e-8)
+    if shared:
+        fd = (_loss(pos, sig + h, val, G, H, W, None) - _loss(pos, sig - h, val, G, H, W, None)) / (2 * h)
+        assert g["grad_sigma"][0] == pytest.approx(fd, rel=1e-6, abs=1e-8)
+
+
+def test_backward_truncated_matches_fd_away_from_boundary():
+    """With truncation, the almost-everywhere gradient equals FD when no pair
+    sits within the FD step of the radius."""
+    H, W, N, C = 9, 9, 10, 1
+    r = 2.0
+    vv, uu = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    for seed in range(31, 100):  # first seed whose pairs all keep a margin to the radius
+        rng = np.random.default_rng(seed)
+        pos = rng.random((1, N, 2)) * [W, H]
+        sig = rng.uniform(0.7, 1.4, (1, N))
+        val = rng.random((1, N, C))
+        G = rng.standard_normal((1, C, H, W))
+        d = np.sqrt((uu[None] - pos[0, :, 0, None, None]) ** 2 + (vv[None] - pos[0, :, 1, None, None]) ** 2)
+        if np.abs(d - r * sig[0, :, None, None]).min() > 1e-4:
+            break
+    else:
+        raise AssertionError("no seed with margin")
+    g = oracle.backward(pos, sig, val, G, H, W, radius=r)
+    h = 1e-7
+    for j in range(N):
+        p1, p2 = pos.copy(), pos.copy()
+        p1[0, j, 0] += h
+        p2[0, j, 0] -= h
+        fd = (_loss(p1, sig, val, G, H, W, r) - _loss(p2, sig, val, G, H, W, r)) / (2 * h)
+        assert g["grad_pos"][0, j, 0] == pytest.approx(fd, rel=1e-5, abs=1e-8)
+
+
+def test_partition_of_unity_for_value_gradient():
+    """sum_j dL/dc_jk = sum over pixels with Z>0 of G_ik, since the weights of a
+    pixel sum to one after normalisation."""
+    wl = synth.random_workload(41, 1, 40, 14, 15, C=3, sigma=(0.3, 0.9))
+    G = wl.grad_out()
+    g = oracle.backward(wl.pos, wl.sigma, wl.values, G, wl.H, wl.W, 3.0)
+    m = g["fwd"]["Z"][0] > 0
+    assert (~m).sum() > 0  # some empty pixels so the mask matters
+    lhs = g["grad_values"][0].sum(axis=0)
+    rhs = np.array([G[0, k][m].astype(np.float64).sum() for k in range(3)])
+    np.testing.assert_allclose(lhs, rhs, rtol=1e-10)
+
+
+def test_constant_colour_has_zero_position_and_sigma_gradient():
+    wl = synth.random_workload(43, 1, 120, 12, 12, C=2, sigma=(0.5, 1.5))
+    val = np.full(wl.values.shape, 0.7, np.float64)
+    G = wl.grad_out()
+    g = oracle.backward(wl.pos, wl.sigma, val, G, wl.H, wl.W, 3.0)
+    assert np.abs(g["grad_pos"]).max() < 1e-12
+    assert np.abs(g["grad_sigma"]).max() < 1e-12
+    assert np.abs(g["grad_values"]).max() > 1e-3
+
+
+def test_two_point_closed_form_gradients():
+    """o(u) = c0 + (c1-c0) s, s = sigmoid(((u-x0)^2 - (u-x1)^2)/(2 sigma^2)) with
+    per-point sigma equal:  do/dc1 = s,  do/dx1 = (c1-c0) s (1-s) (u-x1)/sigma^2,
+    do/dsigma1 = (c1-c0) s (1-s) (u-x1)^2 / sigma^3  (same-row points)."""
+    x0, x1, y0, s = 1.2, 2.9, 0.0, 1.05
+    c0, c1 = 0.3, 1.7
+    W, u = 5, 2
+    pos = np.array([[[x0, y0], [x1, y0]]])
+    sig = np.array([[s, s]])
+    val = np.array([[[c0], [c1]]])
+    G = np.zeros((1, 1, 1, W))
+    G[0, 0, 0, u] = 1.0
+    g = oracle.backward(pos, sig, val, G, 1, W, radius=None)
+    t = ((u - x0) ** 2 - (u - x1) ** 2) / (2 * s * s)
+    sg = _sigmoid(t)
+    assert g["grad_values"][0, 1, 0] == pytest.approx(sg, rel=1e-13)
+    assert g["grad_values"][0, 0, 0] == pytest.approx(1 - sg, rel=1e-13)
+    assert g["grad_pos"][0, 1, 0] == pytest.approx((c1 - c0) * sg * (1 - sg) * (u - x1) / s ** 2, rel=1e-12)
+    assert g["grad_sigma"][0, 1] == pytest.approx((c1 - c0) * sg * (1 - sg) * (u - x1) ** 2 / s ** 3, rel=1e-12)
+    assert g["grad_pos"][0, 1, 1] == pytest.approx(0.0, abs=1e-15)
+
+
+def test_backward_points_subset_matches_full():
+    wl = synth.random_workload(47, 1, 90, 12, 13, C=2, sigma=(0.5, 1.8))
+    G = wl.grad_out()
+    full = oracle.backward(wl.pos, wl.sigma, wl.values, G, wl.H, wl.W, 3.0)
+    pts = [0, 5, 17, 42, 89]
+    sub = oracle.backward_points(wl.pos, wl.sigma, wl.values, G, wl.H, wl.W, 3.0, 0, pts)
+    np.testing.assert_allclose(sub["grad_pos"], full["grad_pos"][0, pts], rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(sub["grad_sigma"], full["grad_sigma"][0, pts], rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(sub["grad_values"], full["grad_values"][0, pts], rtol=1e-12, atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# Bins
+# --------------------------------------------------------------------------
+
+def test_bins_brute_force_and_invariants():
+    T, H, W = 8, 20, 27
+    pts = np.array([[0.0, 0.0], [8.0, 7.9999995], [7.9999995, 8.0], [-3.0, 5.0], [30.0, 19.5],
+                    [26.99, -0.1], [16.0, 16.0], [8.0, 0.5], [3.0, 3.0], [8.0, 0.25],
+                    [40.0, 2.0], [1.0, 33.0], [-1e9, 1e9]], np.float32)
+    pos = pts[None]
+    r = oracle.bins(pos, H, W, T)
+    nbx, nby = 4, 3
+    assert (r["nbx"], r["nby"]) == (nbx, nby)
+    expect = []
+    for x, y in pts:
+        bx = min(max(int(math.floor(float(x) / T)), 0), nbx - 1)
+        by = min(max(int(math.floor(float(y) / T)), 0), nby - 1)
+        expect.append(by * nbx + bx)
+    assert list(r["bin_of"][0]) == expect
+    assert expect[1] == 1 and expect[2] == 4 and expect[3] == 0 and expect[4] == 11
+    assert expect[10] == 3 and expect[11] == 8 and expect[12] == 8
+    order = sorted(range(len(pts)), key=lambda j: (expect[j], j))
+    assert list(r["perm"][0]) == order
+    assert r["count"][0].sum() == len(pts)
+    assert r["offset"][0, 0] == 0 and r["offset"][0, -1] == len(pts)
+    assert np.all(np.diff(r["offset"][0]) == r["count"][0])
+
+
+def test_bins_random_stable_grouped():
+    wl = synth.random_workload(51, 2, 5000, 70, 90, sigma=1.0, blob_frac=0.5)
+    r = oracle.bins(wl.pos, wl.H, wl.W, 16)
+    for b in range(2):
+        perm = r["perm"][b]
+        assert np.array_equal(np.sort(perm), np.arange(wl.N))
+        keys = r["bin_of"][b][perm]
+        assert np.all(np.diff(keys) >= 0)
+        same = np.diff(keys) == 0
+        assert np.all(np.diff(perm)[same] > 0)
+        for k in range(0, r["count"].shape[1], 7):
+            seg = perm[r["offset"][b, k]: r["offset"][b, k + 1]]
+            assert np.all(r["bin_of"][b][seg] == k)
