@@ -51,7 +51,7 @@ from __future__ import annotations
 
 import math
 import os
-from concurrent.futures import ProcessPoolExecutor
+from concurrent.futures import ThreadPoolExecutor
 from typing import Dict, Optional, Sequence
 
 import numpy as np
@@ -139,9 +139,12 @@ def _forward_block(args):
 
 
 def _pool_map(fn, jobs, workers):
+    # threads, not processes: the heavy work is large numpy array operations,
+    # which release the GIL, and a thread pool is safe in a process that has
+    # already initialised a GPU
     if workers <= 1 or len(jobs) <= 1:
         return [fn(j) for j in jobs]
-    with ProcessPoolExecutor(max_workers=workers) as ex:
+    with ThreadPoolExecutor(max_workers=workers) as ex:
         return list(ex.map(fn, jobs))
 
 

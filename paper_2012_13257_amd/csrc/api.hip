@@ -1,0 +1,137 @@
+// extern "C" entry points of libgmminterp.so (declared in include/gmminterp.h):
+// argument validation, buffer carving and kernel dispatch on the caller's
+// stream.  No host synchronisation and no device allocation happen here.
+#include <cstdint>
+#include <cstring>
+#include <string>
+
+#include "common.hpp"
+
+namespace gmm {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int fail_hip(hipError_t e, const char* where) {
+  g_last_error = std::string(where) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+  return INTERP_EHIP;
+}
+
+static bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+// Common validation of forward/backward inputs.  Returns INTERP_OK or an error.
+static int check_io(const interp_problem* prob, Geometry* g, Layout* L, const float* pos,
+                    const float* sigma, const float* values, const void* saved, size_t saved_size,
+                    const void* work, size_t work_size) {
+  std::string m = make_geometry(prob, g);
+  if (!m.empty()) return fail(INTERP_EINVAL, m);
+  *L = make_layout(*g);
+  if (g->N > 0) {
+    if (!pos || !sigma || !values) return fail(INTERP_EINVAL, "pos, sigma and values must not be NULL when N > 0");
+    if (!aligned(pos, 8)) return fail(INTERP_EINVAL, "pos must be 8-byte aligned");
+    if (!aligned(sigma, 4) || !aligned(values, 4)) return fail(INTERP_EINVAL, "sigma and values must be 4-byte aligned");
+  }
+  if (!saved) return fail(INTERP_EINVAL, "saved must not be NULL");
+  if (!work) return fail(INTERP_EINVAL, "workspace must not be NULL");
+  if (!aligned(saved, kAlign) || !aligned(work, kAlign))
+    return fail(INTERP_EINVAL, "saved and workspace must be 256-byte aligned");
+  if (saved_size < L->saved_bytes)
+    return fail(INTERP_EINVAL, "saved buffer too small: need " + std::to_string(L->saved_bytes) +
+                                   " bytes, got " + std::to_string(saved_size));
+  if (work_size < L->work_bytes)
+    return fail(INTERP_EINVAL, "workspace too small: need " + std::to_string(L->work_bytes) +
+                                   " bytes, got " + std::to_string(work_size));
+  return INTERP_OK;
+}
+
+}  // namespace gmm
+
+using namespace gmm;
+
+extern "C" {
+
+size_t interp_workspace_bytes(const interp_problem* prob) {
+  Geometry g;
+  std::string m = make_geometry(prob, &g);
+  if (!m.empty()) { fail(INTERP_EINVAL, m); return 0; }
+  return make_layout(g).work_bytes;
+}
+
+size_t interp_saved_bytes(const interp_problem* prob) {
+  Geometry g;
+  std::string m = make_geometry(prob, &g);
+  if (!m.empty()) { fail(INTERP_EINVAL, m); return 0; }
+  return make_layout(g).saved_bytes;
+}
+
+int interp_forward(const interp_problem* prob, const float* pos, const float* sigma,
+                   const float* values, float* out, void* saved, size_t saved_size,
+                   void* workspace, size_t workspace_size, void* stream) {
+  Geometry g;
+  Layout L;
+  int rc = check_io(prob, &g, &L, pos, sigma, values, saved, saved_size, workspace, workspace_size);
+  if (rc != INTERP_OK) return rc;
+  if (!out || !aligned(out, 4)) return fail(INTERP_EINVAL, "out must be a non-NULL 4-byte aligned pointer");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Views v = make_views(L, saved, workspace);
+  hipError_t e = launch_binning(g, pos, sigma, values, v, st);
+  if (e != hipSuccess) return fail_hip(e, "binning kernels");
+  e = launch_forward(g, v, out, st);
+  if (e != hipSuccess) return fail_hip(e, "forward kernel");
+  g_last_error.clear();
+  return INTERP_OK;
+}
+
+int interp_backward(const interp_problem* prob, const float* pos, const float* sigma,
+                    const float* values, const float* out, const void* saved, size_t saved_size,
+                    const float* grad_out, float* grad_pos, float* grad_sigma, float* grad_values,
+                    void* workspace, size_t workspace_size, void* stream) {
+  Geometry g;
+  Layout L;
+  int rc = check_io(prob, &g, &L, pos, sigma, values, saved, saved_size, workspace, workspace_size);
+  if (rc != INTERP_OK) return rc;
+  if (!out || !grad_out) return fail(INTERP_EINVAL, "out and grad_out must not be NULL");
+  if (!aligned(grad_out, 4) || !aligned(out, 4)) return fail(INTERP_EINVAL, "out and grad_out must be 4-byte aligned");
+  if (grad_pos && !aligned(grad_pos, 8)) return fail(INTERP_EINVAL, "grad_pos must be 8-byte aligned");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Views v = make_views(L, const_cast<void*>(saved), workspace);
+  hipError_t e = launch_backward(g, sigma, out, grad_out, grad_pos, grad_sigma, grad_values, v, st);
+  if (e != hipSuccess) return fail_hip(e, "backward kernels");
+  g_last_error.clear();
+  return INTERP_OK;
+}
+
+int interp_debug_bins(const interp_problem* prob, const void* saved, size_t saved_size,
+                      const void* workspace, size_t workspace_size, int32_t* bin_of, int32_t* count,
+                      int32_t* offset, int32_t* perm, void* stream) {
+  Geometry g;
+  std::string m = make_geometry(prob, &g);
+  if (!m.empty()) return fail(INTERP_EINVAL, m);
+  Layout L = make_layout(g);
+  if (!saved || !workspace || saved_size < L.saved_bytes || workspace_size < L.work_bytes)
+    return fail(INTERP_EINVAL, "saved/workspace missing or too small");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const char* s = static_cast<const char*>(saved);
+  const char* w = static_cast<const char*>(workspace);
+  const size_t BN = size_t(g.B) * g.N * 4;
+  struct Cp { void* dst; const void* src; size_t n; } cps[4] = {
+      {bin_of, w + L.binof, BN},
+      {count, w + L.count, size_t(g.B) * g.nb * 4},
+      {offset, s + L.offset, size_t(g.B) * (g.nb + 1) * 4},
+      {perm, s + L.perm, BN}};
+  for (auto& c : cps) {
+    if (!c.dst || c.n == 0) continue;
+    hipError_t e = hipMemcpyAsync(c.dst, c.src, c.n, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return fail_hip(e, "interp_debug_bins copy");
+  }
+  g_last_error.clear();
+  return INTERP_OK;
+}
+
+const char* interp_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

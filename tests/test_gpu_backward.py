@@ -1,0 +1,128 @@
+"""GPU parity of the backward (adjoint) kernels against the oracle's analytic
+gradient, finite differences, and the autograd binding."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2012_13257_amd import synth
+from gpu_helpers import check_grad, run_forward, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_grads(wl, G, tile=8):
+    import torch
+    from paper_2012_13257_amd import interp
+    out, saved, work, (pos, sig, val) = run_forward(wl, tile)
+    Gt = torch.from_numpy(np.ascontiguousarray(G)).cuda()
+    gp, gs, gv = interp.backward(pos, sig, val, out, saved, Gt)
+    torch.cuda.synchronize()
+    return gp.cpu().numpy(), gs.cpu().numpy(), gv.cpu().numpy()
+
+
+def _full_backward_check(wl, tile=8):
+    say("backward full", wl.name, wl.B, wl.N, wl.C, wl.H, wl.W)
+    G = wl.grad_out()
+    gp, gs, gv = _gpu_grads(wl, G, tile)
+    ref = oracle.backward(wl.pos, wl.sigma, wl.values, G, wl.H, wl.W, wl.radius,
+                          workers=oracle.default_workers())
+    e1 = check_grad(gp, ref["grad_pos"], ref["scale_pos"], wl.name + " pos")
+    e2 = check_grad(gv, ref["grad_values"], ref["scale_values"], wl.name + " values")
+    e3 = check_grad(gs, ref["grad_sigma"], ref["scale_sigma"], wl.name + " sigma")
+    return e1, e2, e3
+
+
+def test_backward_cfg1_full():
+    _full_backward_check(synth.config1())
+
+
+@pytest.mark.parametrize("C", [1, 3, 4, 8, 16])
+def test_backward_per_point_sigma_multitile(C):
+    _full_backward_check(synth.random_workload(700 + C, 2, 500, 26, 37, C=C, sigma=(0.5, 2.0),
+                                               values="normal", blob_frac=0.5, blob_std=(2.0, 5.0)))
+
+
+def test_backward_shared_sigma_batch():
+    _full_backward_check(synth.random_workload(751, 3, 400, 24, 30, C=3, sigma=0.9))
+
+
+def test_backward_cfg3_sampled_points():
+    wl = synth.config3()
+    say("backward cfg3 sampled")
+    G = wl.grad_out()
+    gp, gs, gv = _gpu_grads(wl, G)
+    rng = np.random.default_rng(77)
+    pts = rng.choice(wl.N, 48, replace=False)
+    ref = oracle.backward_points(wl.pos, wl.sigma, wl.values, G, wl.H, wl.W, wl.radius, 0, pts,
+                                 workers=oracle.default_workers(), block=3)
+    check_grad(gp[0, pts], ref["grad_pos"], ref["scale_pos"], "cfg3 pos")
+    check_grad(gv[0, pts], ref["grad_values"], ref["scale_values"], "cfg3 values")
+    check_grad(gs[0, pts], ref["grad_sigma"], ref["scale_sigma"], "cfg3 sigma")
+
+
+def test_backward_partition_of_unity_cfg3():
+    """sum_j dL/dc_jk equals the sum of G over pixels with Z > 0 (any size)."""
+    import torch
+    from gpu_helpers import saved_Z
+    from paper_2012_13257_amd import interp
+    wl = synth.config3()
+    G = wl.grad_out()
+    out, saved, work, (pos, sig, val) = run_forward(wl)
+    Gt = torch.from_numpy(G).cuda()
+    _, _, gv = interp.backward(pos, sig, val, out, saved, Gt, need_pos=False, need_sigma=False)
+    m = (saved_Z(saved) > 0).double()
+    lhs = gv.double().sum(dim=1)[0]
+    rhs = (Gt.double() * m[:, None]).sum(dim=(2, 3))[0]
+    absG = (Gt.double().abs() * m[:, None]).sum(dim=(2, 3))[0]
+    assert torch.all((lhs - rhs).abs() <= 1e-4 * absG)
+
+
+def test_backward_matches_gpu_finite_differences():
+    """Directional FD of the GPU forward itself (float32, loose tolerance): the
+    backward is the derivative of what the forward computes."""
+    import torch
+    from paper_2012_13257_amd import interp
+    wl = synth.random_workload(801, 1, 300, 24, 24, C=2, sigma=(0.8, 2.0))
+    pos, sig, val = to_dev(wl)
+    G = torch.from_numpy(wl.grad_out()).cuda()
+    out, saved, _ = interp.forward(pos, sig, val, wl.H, wl.W, 3.0)
+    gp, gs, gv = interp.backward(pos, sig, val, out, saved, G)
+    rng = np.random.default_rng(9)
+    d = torch.from_numpy(rng.standard_normal(wl.values.shape).astype(np.float32)).cuda()
+    h = 1e-2
+    lp = (interp.forward(pos, sig, val + h * d, wl.H, wl.W, 3.0)[0].double() * G).sum()
+    lm = (interp.forward(pos, sig, val - h * d, wl.H, wl.W, 3.0)[0].double() * G).sum()
+    fd = float((lp - lm) / (2 * h))
+    an = float((gv.double() * d).sum())
+    assert fd == pytest.approx(an, rel=2e-3)
+
+
+def test_autograd_function_matches_backward():
+    import torch
+    from paper_2012_13257_amd import interp
+    wl = synth.random_workload(811, 2, 400, 20, 28, C=3, sigma=(0.5, 1.5))
+    pos, sig, val = to_dev(wl)
+    pos.requires_grad_(True)
+    sig.requires_grad_(True)
+    val.requires_grad_(True)
+    out = interp.interpolate(pos, sig, val, wl.H, wl.W, 3.0)
+    G = torch.from_numpy(wl.grad_out()).cuda()
+    (out * G).sum().backward()
+    out2, saved, _ = interp.forward(pos.detach(), sig.detach(), val.detach(), wl.H, wl.W, 3.0)
+    gp, gs, gv = interp.backward(pos.detach(), sig.detach(), val.detach(), out2, saved, G)
+    assert torch.equal(out, out2)
+    assert torch.equal(pos.grad, gp) and torch.equal(sig.grad, gs) and torch.equal(val.grad, gv)
+    # only the values need a gradient: the others are not computed
+    v2 = val.detach().clone().requires_grad_(True)
+    interp.interpolate(pos.detach(), sig.detach(), v2, wl.H, wl.W, 3.0).mul(G).sum().backward()
+    assert torch.equal(v2.grad, gv)
+
+
+def test_backward_deterministic():
+    wl = synth.random_workload(821, 1, 5000, 64, 64, C=3, sigma=(0.5, 2.0), blob_frac=0.6,
+                               blob_std=(4.0, 9.0))
+    G = wl.grad_out()
+    a = _gpu_grads(wl, G)
+    b = _gpu_grads(wl, G)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
