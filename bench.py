@@ -1,0 +1,277 @@
+#!/usr/bin/env python3
+"""Benchmark of the Gaussian-mixture interpolation hot path on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+A step is one interp_forward + interp_backward (binning, forward gather,
+backward prologue and adjoint; gradients w.r.t. positions, sigma and values)
+on the 1024x1024, N=2^20, C=3, per-point-sigma workload, inputs resident in
+HBM.  Prints ONE JSON line with the output Mpix/s of fwd+bwd (`value`), the
+forward-only Mpix/s, the roofline of the dominant kernel, the CPU oracle
+baseline and, when the serving loop is built, its p50/p99 latency.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published peaks and derived ALU issue rate (see the design notes)
+HBM_PEAK_GBS = 8000.0
+CU, SIMD_LANES_PER_CU, CLOCK_GHZ = 256, 64, 2.4
+VALU_PEAK_TLANEOPS = CU * SIMD_LANES_PER_CU * CLOCK_GHZ / 1000.0   # 39.32 T lane-ops/s
+EXP_SLOTS = 4  # v_exp_f32 is a quarter-rate transcendental: 4 issue slots per lane
+
+
+def pair_count(pos: np.ndarray, sigma: np.ndarray, H: int, W: int, radius: float) -> int:
+    """Exact number of (pixel, point) pairs passing the float32 radius test,
+    enumerated per point over its bounding box (the work unit of the roofline)."""
+    total = 0
+    B, N, _ = pos.shape
+    f32 = np.float32
+    for b in range(B):
+        sig = sigma[b] if sigma.ndim == 2 else np.full(N, sigma[b], np.float32)
+        rs = (f32(radius) * sig.astype(np.float32)).astype(np.float32)
+        R2 = (rs * rs).astype(np.float32)
+        reach = np.ceil(rs.astype(np.float64) + 1.0).astype(np.int64)
+        x = pos[b, :, 0]
+        y = pos[b, :, 1]
+        for rch in np.unique(reach):
+            sel = np.nonzero(reach == rch)[0]
+            offs = np.arange(-rch, rch + 1)
+            for chunk in range(0, sel.size, 65536):
+                s = sel[chunk: chunk + 65536]
+                u = np.floor(x[s]).astype(np.int64)[:, None] + offs[None, :]
+                v = np.floor(y[s]).astype(np.int64)[:, None] + offs[None, :]
+                dx = (u.astype(np.float32) - x[s, None]).astype(np.float32)
+                dy = (v.astype(np.float32) - y[s, None]).astype(np.float32)
+                dxx = (dx * dx).astype(np.float32)
+                dyy = (dy * dy).astype(np.float32)
+                okx = (u >= 0) & (u < W)
+                oky = (v >= 0) & (v < H)
+                d2 = (dxx[:, None, :] + dyy[:, :, None]).astype(np.float32)
+                inc = (d2 <= R2[s, None, None]) & okx[:, None, :] & oky[:, :, None]
+                total += int(inc.sum())
+    return total
+
+
+def _to_dev(wl):
+    import torch
+    return (torch.from_numpy(wl.pos).cuda(), torch.from_numpy(wl.sigma).cuda(),
+            torch.from_numpy(wl.values).cuda())
+
+
+def time_steps(fn, steps: int, warmup: int, profile: bool):
+    import torch
+    from paper_2012_13257_amd import _lib
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    if profile:
+        _lib.profile_enable(True)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    for _ in range(steps):
+        fn()
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = start.elapsed_time(stop) / steps
+    kernels = {}
+    if profile:
+        for name in ("bin_keys", "radix_hist", "radix_scan", "radix_scatter", "bin_finish",
+                     "bin_gather", "forward", "bwd_pixel", "bwd_point", "bwd_sigma_sum"):
+            tot, n = _lib.profile_read(name)
+            if n:
+                kernels[name] = {"avg_us": 1000.0 * tot / n, "launches": n}
+        _lib.profile_enable(False)
+    return ms, wall, kernels
+
+
+def cpu_baseline(wl, G, budget_s: float):
+    """The oracle as it stands, on a bounded sample of the same workload."""
+    import oracle
+    workers = oracle.default_workers()
+    rng = np.random.default_rng(2024)
+    # forward: a pixel sample sized to about half the budget (calibrated on 16 pixels)
+    t0 = time.perf_counter()
+    px = 16
+    oracle.forward_pixels(wl.pos, wl.sigma, wl.values, wl.radius, np.zeros(px, np.int64),
+                          rng.integers(0, wl.H, px), rng.integers(0, wl.W, px), workers=1)
+    t_px1 = (time.perf_counter() - t0) / px
+    n_px = int(max(64, min(20000, 0.5 * budget_s * workers / max(t_px1, 1e-6))))
+    b = np.zeros(n_px, np.int64)
+    v = rng.integers(0, wl.H, n_px)
+    u = rng.integers(0, wl.W, n_px)
+    t0 = time.perf_counter()
+    oracle.forward_pixels(wl.pos, wl.sigma, wl.values, wl.radius, b, v, u, workers=workers)
+    t_fwd = (time.perf_counter() - t0) / n_px
+    # backward: a point sample (each point recomputes Z and out at its support)
+    t0 = time.perf_counter()
+    oracle.backward_points(wl.pos, wl.sigma, wl.values, G, wl.H, wl.W, wl.radius, 0, [0], workers=1)
+    t_pt1 = time.perf_counter() - t0
+    n_pt = int(max(4, min(4096, 0.5 * budget_s * workers / max(t_pt1, 1e-6))))
+    pts = rng.choice(wl.N, n_pt, replace=False)
+    t0 = time.perf_counter()
+    oracle.backward_points(wl.pos, wl.sigma, wl.values, G, wl.H, wl.W, wl.radius, 0, pts,
+                           workers=workers, block=max(1, n_pt // (4 * workers)))
+    t_bwd = (time.perf_counter() - t0) / n_pt
+    per_px = t_fwd + t_bwd * (wl.N / (wl.H * wl.W))
+    return {"value": 1.0 / per_px / 1e6, "unit": "Mpix/s (fwd+bwd)", "cores": workers,
+            "kind": "oracle",
+            "sample": f"{n_px} random pixels forward + {n_pt} random points backward of the "
+                      f"{wl.H}x{wl.W} N={wl.N} workload, extrapolated linearly to the full image "
+                      f"(fwd {t_fwd * 1e3:.2f} ms/pixel, bwd {t_bwd * 1e3:.1f} ms/point)",
+            "fwd_mpix_s": 1.0 / t_fwd / 1e6}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-budget", type=float, default=12.0,
+                    help="seconds of CPU work for the oracle baseline (0 disables)")
+    ap.add_argument("--no-serving", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2012_13257_amd import interp, synth, _lib
+
+    if not torch.cuda.is_available():
+        print("bench.py needs the ROCm device", file=sys.stderr)
+        sys.exit(1)
+    log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)  # noqa: E731
+
+    wl = synth.config3()
+    G_np = wl.grad_out()
+    log("workload", wl.name, "B", wl.B, "N", wl.N, "C", wl.C, "HxW", wl.H, wl.W)
+    pos, sig, val = _to_dev(wl)
+    G = torch.from_numpy(G_np).cuda()
+    prob = interp.problem(pos, sig, val, wl.H, wl.W, wl.radius)
+    import ctypes
+    L = _lib.lib()
+    out = torch.empty((wl.B, wl.C, wl.H, wl.W), device="cuda")
+    saved = interp.Saved(prob, pos.device)
+    work = interp.Workspace(prob, pos.device)
+    gp = torch.empty_like(pos)
+    gs = torch.empty_like(sig)
+    gv = torch.empty_like(val)
+    stream = torch.cuda.current_stream().cuda_stream
+    pb = ctypes.byref(prob)
+
+    def fwd():
+        _lib.check("interp_forward", L.interp_forward(
+            pb, pos.data_ptr(), sig.data_ptr(), val.data_ptr(), out.data_ptr(), saved.addr,
+            saved.nbytes, work.addr, work.nbytes, stream))
+
+    def bwd():
+        _lib.check("interp_backward", L.interp_backward(
+            pb, pos.data_ptr(), sig.data_ptr(), val.data_ptr(), out.data_ptr(), saved.addr,
+            saved.nbytes, G.data_ptr(), gp.data_ptr(), gs.data_ptr(), gv.data_ptr(), work.addr,
+            work.nbytes, stream))
+
+    def step():
+        fwd()
+        bwd()
+
+    ms_step, wall, kernels = time_steps(step, args.steps, args.warmup, profile=True)
+    log(f"fwd+bwd {ms_step * 1e3:.1f} us/step (wall {wall / args.steps * 1e6:.1f} us/step)")
+    ms_fwd, _, kernels_fwd = time_steps(fwd, args.steps, args.warmup, profile=True)
+    log(f"fwd {ms_fwd * 1e3:.1f} us/step")
+    for k, v in kernels.items():
+        log(f"  {k:16s} {v['avg_us']:9.2f} us x{v['launches']}")
+
+    pix = wl.B * wl.H * wl.W
+    value = pix / (ms_step * 1e-3) / 1e6
+    fwd_mpix = pix / (ms_fwd * 1e-3) / 1e6
+
+    t0 = time.perf_counter()
+    P = pair_count(wl.pos, wl.sigma, wl.H, wl.W, wl.radius)
+    log(f"pairs inside the radius P = {P} ({time.perf_counter() - t0:.1f} s to count)")
+    C = wl.C
+    ops_fwd_pair = 8 + C + EXP_SLOTS          # d2 (5), k*d2, cmp/select, Z add, C FMAs; exp
+    ops_bwd_pair = 13 + 2 * C + EXP_SLOTS     # d2 (3 with the row term), exp arg, A (C), gc (C), 4 for x/y/s
+    dom = max(kernels.items(), key=lambda kv: kv[1]["avg_us"])
+    name, info = dom
+    if name == "forward":
+        work_units = P * ops_fwd_pair
+    elif name == "bwd_point":
+        work_units = P * ops_bwd_pair
+    else:
+        work_units = None
+    roof = None
+    if work_units is not None:
+        achieved = work_units / (info["avg_us"] * 1e-6) / 1e12
+        roof = {"bound": "alu", "kernel": name, "achieved": round(achieved, 3),
+                "peak": round(VALU_PEAK_TLANEOPS, 2), "unit": "Tlaneop/s",
+                "frac": round(achieved / VALU_PEAK_TLANEOPS, 4), "traffic": None,
+                "work_per_launch": f"P={P} pairs x {ops_fwd_pair if name == 'forward' else ops_bwd_pair} "
+                                   "lane-op slots (exp = 4)",
+                "kernel_avg_us": round(info["avg_us"], 2)}
+    other = {}
+    for kname, ops in (("forward", ops_fwd_pair), ("bwd_point", ops_bwd_pair)):
+        if kname in kernels:
+            a = P * ops / (kernels[kname]["avg_us"] * 1e-6) / 1e12
+            other[kname] = {"avg_us": round(kernels[kname]["avg_us"], 2),
+                            "alu_frac": round(a / VALU_PEAK_TLANEOPS, 4)}
+
+    cpu = None
+    if args.cpu_budget > 0:
+        log("timing the CPU oracle baseline ...")
+        cpu = cpu_baseline(wl, G_np, args.cpu_budget)
+        log(f"oracle {cpu['value']:.3g} Mpix/s fwd+bwd on {cpu['cores']} threads")
+
+    serving = None
+    if not args.no_serving:
+        try:
+            from paper_2012_13257_amd import serving_bench
+            serving = serving_bench.run(log)
+        except ImportError:
+            serving = None
+
+    res = {
+        "metric": "output Mpix/s fwd+bwd at 1024x1024, N=1M (fwd-only and serving p50/p99 alongside)",
+        "value": round(value, 2),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded: 70% of points in 8 Gaussian blobs, 30% uniform)",
+        "config": {"workload": wl.name, "B": wl.B, "H": wl.H, "W": wl.W, "N": wl.N, "C": wl.C,
+                   "sigma": "per point, log-uniform [0.5, 2]", "radius": wl.radius, "tile": 8,
+                   "pairs_in_radius": P},
+        "fwd_mpix_s": round(fwd_mpix, 2),
+        "fwd_ms": round(ms_fwd, 4),
+        "kernels_us": {k: round(v["avg_us"], 2) for k, v in kernels.items()},
+        "kernel_alu": other,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "serving": serving,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

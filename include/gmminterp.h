@@ -138,6 +138,18 @@ int interp_debug_bins(const interp_problem* prob, const void* saved, size_t save
 /* Thread-local message describing the last error of this thread ("" if none). */
 const char* interp_last_error(void);
 
+/* Measurement hooks for benchmarks.  While enabled, every kernel the library
+ * launches outside HIP graph capture is bracketed by a pair of HIP events on
+ * the stream it is launched on.  interp_profile_enable(1) also clears the
+ * previous records; interp_profile_enable(0) stops recording.
+ * interp_profile_read waits for the recorded kernels and returns, summed over
+ * the kernels whose name starts with `prefix` ("" for all), the total
+ * duration in milliseconds and the number of launches.  Kernel names:
+ * bin_keys, radix_hist, radix_scan, radix_scatter, bin_finish, bin_gather,
+ * forward, bwd_pixel, bwd_point, bwd_sigma_sum. */
+int interp_profile_enable(int on);
+int interp_profile_read(const char* prefix, double* total_ms, int64_t* launches);
+
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of independent interpolation requests.
  *

@@ -53,7 +53,8 @@ class Status(ctypes.Structure):
 # every symbol include/gmminterp.h declares
 EXPORTS = [
     "interp_workspace_bytes", "interp_saved_bytes", "interp_forward", "interp_backward",
-    "interp_debug_bins", "interp_last_error", "interp_server_create", "interp_submit",
+    "interp_debug_bins", "interp_last_error", "interp_profile_enable", "interp_profile_read",
+    "interp_server_create", "interp_submit",
     "interp_poll", "interp_server_drain", "interp_server_destroy",
 ]
 
@@ -78,6 +79,11 @@ def _declare(L):
     L.interp_debug_bins.restype = ctypes.c_int
     L.interp_last_error.argtypes = []
     L.interp_last_error.restype = ctypes.c_char_p
+    L.interp_profile_enable.argtypes = [ctypes.c_int]
+    L.interp_profile_enable.restype = ctypes.c_int
+    L.interp_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_int64)]
+    L.interp_profile_read.restype = ctypes.c_int
     if not hasattr(L, "interp_server_create"):
         return
     L.interp_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(c_void_p)]
@@ -115,6 +121,19 @@ class InterpError(RuntimeError):
     def __init__(self, fn: str, code: int, msg: str):
         super().__init__(f"{fn} failed with code {code}: {msg}")
         self.code = code
+
+
+def profile_enable(on: bool) -> None:
+    check("interp_profile_enable", lib().interp_profile_enable(1 if on else 0))
+
+
+def profile_read(prefix: str = ""):
+    """(total milliseconds, launches) of the recorded kernels whose name starts with prefix."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    check("interp_profile_read", lib().interp_profile_read(prefix.encode(), ctypes.byref(ms),
+                                                            ctypes.byref(n)))
+    return ms.value, n.value
 
 
 def check(fn: str, rc: int) -> None:

@@ -22,7 +22,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libgmminterp.so")
 
-SOURCES = ["api.hip", "bins.hip", "forward.hip", "backward.hip", "server.hip"]
+SOURCES = ["api.hip", "single.hip", "server.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -1,9 +1,12 @@
 // extern "C" entry points of libgmminterp.so (declared in include/gmminterp.h):
 // argument validation, buffer carving and kernel dispatch on the caller's
 // stream.  No host synchronisation and no device allocation happen here.
+#include <atomic>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "common.hpp"
 
@@ -19,6 +22,51 @@ int fail(int code, const std::string& msg) {
 int fail_hip(hipError_t e, const char* where) {
   g_last_error = std::string(where) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
   return INTERP_EHIP;
+}
+
+// ---------------------------------------------------------------------------
+// Per-kernel event timing
+// ---------------------------------------------------------------------------
+namespace {
+struct ProfRecord {
+  std::string name;
+  hipEvent_t start, stop;
+};
+std::mutex g_prof_mu;
+std::vector<ProfRecord> g_prof;
+std::atomic<int> g_prof_on{0};
+
+void prof_clear_locked() {
+  for (auto& r : g_prof) {
+    hipEventDestroy(r.start);
+    hipEventDestroy(r.stop);
+  }
+  g_prof.clear();
+}
+}  // namespace
+
+ProfRange::ProfRange(const char* name, hipStream_t s) : token(-1), st(s) {
+  if (!g_prof_on.load(std::memory_order_relaxed)) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+  ProfRecord r{name, nullptr, nullptr};
+  if (hipEventCreate(&r.start) != hipSuccess) return;
+  if (hipEventCreate(&r.stop) != hipSuccess) { hipEventDestroy(r.start); return; }
+  hipEventRecord(r.start, st);
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  token = (int)g_prof.size();
+  g_prof.push_back(r);
+}
+
+ProfRange::~ProfRange() {
+  if (token < 0) return;
+  hipEvent_t stop;
+  {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    if (token >= (int)g_prof.size()) return;
+    stop = g_prof[token].stop;
+  }
+  hipEventRecord(stop, st);
 }
 
 static bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
@@ -77,11 +125,10 @@ int interp_forward(const interp_problem* prob, const float* pos, const float* si
   if (rc != INTERP_OK) return rc;
   if (!out || !aligned(out, 4)) return fail(INTERP_EINVAL, "out must be a non-NULL 4-byte aligned pointer");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  Views v = make_views(L, saved, workspace);
-  hipError_t e = launch_binning(g, pos, sigma, values, v, st);
-  if (e != hipSuccess) return fail_hip(e, "binning kernels");
-  e = launch_forward(g, v, out, st);
-  if (e != hipSuccess) return fail_hip(e, "forward kernel");
+  const ImageView v0 = make_view(g, L, saved, workspace, pos, sigma, values, out, nullptr, nullptr,
+                                 nullptr, nullptr);
+  hipError_t e = launch_forward_all(g, v0, st);
+  if (e != hipSuccess) return fail_hip(e, "forward kernels");
   g_last_error.clear();
   return INTERP_OK;
 }
@@ -98,8 +145,9 @@ int interp_backward(const interp_problem* prob, const float* pos, const float* s
   if (!aligned(grad_out, 4) || !aligned(out, 4)) return fail(INTERP_EINVAL, "out and grad_out must be 4-byte aligned");
   if (grad_pos && !aligned(grad_pos, 8)) return fail(INTERP_EINVAL, "grad_pos must be 8-byte aligned");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  Views v = make_views(L, const_cast<void*>(saved), workspace);
-  hipError_t e = launch_backward(g, sigma, out, grad_out, grad_pos, grad_sigma, grad_values, v, st);
+  const ImageView v0 = make_view(g, L, const_cast<void*>(saved), workspace, pos, sigma, values,
+                                 const_cast<float*>(out), grad_out, grad_pos, grad_sigma, grad_values);
+  hipError_t e = launch_backward_all(g, v0, st);
   if (e != hipSuccess) return fail_hip(e, "backward kernels");
   g_last_error.clear();
   return INTERP_OK;
@@ -118,9 +166,8 @@ int interp_debug_bins(const interp_problem* prob, const void* saved, size_t save
   const char* s = static_cast<const char*>(saved);
   const char* w = static_cast<const char*>(workspace);
   const size_t BN = size_t(g.B) * g.N * 4;
-  struct Cp { void* dst; const void* src; size_t n; } cps[4] = {
+  struct Cp { void* dst; const void* src; size_t n; } cps[3] = {
       {bin_of, w + L.binof, BN},
-      {count, w + L.count, size_t(g.B) * g.nb * 4},
       {offset, s + L.offset, size_t(g.B) * (g.nb + 1) * 4},
       {perm, s + L.perm, BN}};
   for (auto& c : cps) {
@@ -128,10 +175,45 @@ int interp_debug_bins(const interp_problem* prob, const void* saved, size_t save
     hipError_t e = hipMemcpyAsync(c.dst, c.src, c.n, hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return fail_hip(e, "interp_debug_bins copy");
   }
+  if (count) {
+    const ImageView v0 = make_view(g, L, const_cast<void*>(saved), const_cast<void*>(workspace),
+                                   nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                   nullptr);
+    hipError_t e = launch_debug_count(g, v0, count, st);
+    if (e != hipSuccess) return fail_hip(e, "interp_debug_bins count");
+  }
   g_last_error.clear();
   return INTERP_OK;
 }
 
 const char* interp_last_error(void) { return g_last_error.c_str(); }
+
+int interp_profile_enable(int on) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  if (on) prof_clear_locked();
+  g_prof_on.store(on ? 1 : 0);
+  return INTERP_OK;
+}
+
+int interp_profile_read(const char* prefix, double* total_ms, int64_t* launches) {
+  if (!prefix || !total_ms || !launches) return fail(INTERP_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  const size_t np = std::strlen(prefix);
+  double tot = 0.0;
+  int64_t n = 0;
+  for (auto& r : g_prof) {
+    if (r.name.compare(0, np, prefix) != 0) continue;
+    hipError_t e = hipEventSynchronize(r.stop);
+    if (e != hipSuccess) return fail_hip(e, "interp_profile_read");
+    float ms = 0.0f;
+    e = hipEventElapsedTime(&ms, r.start, r.stop);
+    if (e != hipSuccess) return fail_hip(e, "interp_profile_read");
+    tot += ms;
+    ++n;
+  }
+  *total_ms = tot;
+  *launches = n;
+  return INTERP_OK;
+}
 
 }  // extern "C"

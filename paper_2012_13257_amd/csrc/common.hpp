@@ -1,5 +1,6 @@
 // Shared host/device definitions of libgmminterp: problem geometry, buffer
-// layouts of the saved state and the workspace, and launch helpers.
+// layouts of the saved state and the workspace, and the per-image view every
+// kernel body works on.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -13,10 +14,12 @@
 namespace gmm {
 
 constexpr int kBlockSide = 8;          // one wavefront owns an 8x8 pixel block
-constexpr int kWave = 64;
 constexpr int kMaxChannels = 32;
-constexpr float kMaxRadius = 12.0f;    // exp2 of -r^2/2*log2(e) stays a normal float
+constexpr float kMaxRadius = 12.0f;    // keeps exp2(-r^2/2 * log2(e)) a normal float
 constexpr size_t kAlign = 256;
+constexpr int kRadixItems = 8;         // keys per thread in a radix pass
+constexpr int kRadixTile = 256 * kRadixItems;  // keys per workgroup in a radix pass
+constexpr int kRadixMaxPasses = 4;     // bin keys of up to 32 bits
 
 inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
 
@@ -33,6 +36,15 @@ inline int col_stride(int C) { int t = channel_template(C); return t < 4 ? 4 : t
 // Floats per backward pixel record (G'_0..G'_{CT-1}, beta), 16-byte multiple.
 inline int pix_stride(int C) { return (channel_template(C) + 1 + 3) / 4 * 4; }
 
+// Radix-sort plan for bin keys in [0, nb): number of passes and digit width.
+inline void radix_plan(int nb, int* npass, int* dbits, int* kbits) {
+  int bits = 0;
+  while ((1LL << bits) < nb) ++bits;
+  *kbits = bits;
+  *npass = (bits + 7) / 8;
+  *dbits = *npass ? (bits + *npass - 1) / *npass : 0;
+}
+
 struct Geometry {
   int B, N, C, H, W, T;
   int nbx, nby, nb;
@@ -40,6 +52,9 @@ struct Geometry {
   float radius;
   int per_point;
   int bx_blocks, by_blocks;            // 8x8 pixel blocks per image row / column
+  int npass, dbits, kbits;             // radix sort of the bin keys
+  int ntiles;                          // radix tiles per image
+  int units256;                        // ceil(N / 256)
 };
 
 // Byte offsets of every array inside the saved buffer and the workspace.
@@ -47,10 +62,8 @@ struct Layout {
   // saved
   size_t Z, reach, offset, perm, geo, col, saved_bytes;
   // workspace
-  size_t count, slot, binof, tmp, prec, gpart, work_bytes;
+  size_t binof, keysF, kA, vA, kB, vB, hist, rpart, prec, gpart, work_bytes;
 };
-
-inline int bwd_groups_per_image(const Geometry& g) { return (g.N + 255) / 256; }
 
 inline Layout make_layout(const Geometry& g) {
   Layout L{};
@@ -64,12 +77,16 @@ inline Layout make_layout(const Geometry& g) {
   L.col = o;    o = align_up(o + B * N * size_t(g.CS) * 4);
   L.saved_bytes = o;
   o = 0;
-  L.count = o;  o = align_up(o + B * size_t(g.nb) * 4);
-  L.slot = o;   o = align_up(o + B * N * 4);
   L.binof = o;  o = align_up(o + B * N * 4);
-  L.tmp = o;    o = align_up(o + B * N * 4);
+  L.keysF = o;  o = align_up(o + B * N * 4);
+  L.kA = o;     o = align_up(o + B * N * 4);
+  L.vA = o;     o = align_up(o + B * N * 4);
+  L.kB = o;     o = align_up(o + B * N * 4);
+  L.vB = o;     o = align_up(o + B * N * 4);
+  L.hist = o;   o = align_up(o + B * size_t(256) * g.ntiles * 4);
+  L.rpart = o;  o = align_up(o + B * size_t(g.units256) * 4 + 4);
   L.prec = o;   o = align_up(o + B * HW * size_t(g.CP) * 4);
-  L.gpart = o;  o = align_up(o + B * size_t(bwd_groups_per_image(g)) * 4 + 4);
+  L.gpart = o;  o = align_up(o + B * size_t(g.units256) * 4 + 4);
   L.work_bytes = o;
   return L;
 }
@@ -83,13 +100,13 @@ inline std::string make_geometry(const interp_problem* p, Geometry* g) {
   if (p->H < 1 || p->W < 1 || p->H > 32768 || p->W > 32768) return "H and W must be in [1, 32768]";
   if (!(p->radius > 0.0f) || !(p->radius <= kMaxRadius)) return "radius must be in (0, 12]";
   if (p->sigma_per_point != 0 && p->sigma_per_point != 1) return "sigma_per_point must be 0 or 1";
-  int T = p->tile == 0 ? 8 : p->tile;
+  const int T = p->tile == 0 ? 8 : p->tile;
   if (T != 4 && T != 8 && T != 16 && T != 32 && T != 64) return "tile must be 0, 4, 8, 16, 32 or 64";
   const long long BN = (long long)p->B * p->N;
   const long long BHW = (long long)p->B * p->H * p->W;
   if (BN >= (1LL << 31)) return "B*N must be below 2^31";
   if (BHW >= (1LL << 31)) return "B*H*W must be below 2^31";
-  if ((long long)p->B * p->N * channel_template(p->C) >= (1LL << 31)) return "B*N*C must be below 2^31";
+  if (BN * channel_template(p->C) >= (1LL << 31)) return "B*N*C must be below 2^31";
   if (BHW * pix_stride(p->C) >= (1LL << 31)) return "B*H*W*(C+1) must be below 2^31";
   g->B = p->B; g->N = p->N; g->C = p->C; g->H = p->H; g->W = p->W; g->T = T;
   g->nbx = (p->W + T - 1) / T;
@@ -102,50 +119,135 @@ inline std::string make_geometry(const interp_problem* p, Geometry* g) {
   g->per_point = p->sigma_per_point;
   g->bx_blocks = (p->W + kBlockSide - 1) / kBlockSide;
   g->by_blocks = (p->H + kBlockSide - 1) / kBlockSide;
+  radix_plan(g->nb, &g->npass, &g->dbits, &g->kbits);
+  g->ntiles = (p->N + kRadixTile - 1) / kRadixTile;
+  g->units256 = (p->N + 255) / 256;
   return "";
 }
 
-// Device view of the saved state and the workspace.
-struct Views {
-  float* Z;
-  float* reach;      // per image: conservative neighbour reach in pixels
-  int* offset;       // [B, nb+1]
-  int* perm;         // [B, N]
-  float4* geo;       // [B, N] sorted (x, y, k, R2), k = -log2(e)/(2 sigma^2)
-  float* col;        // [B, N, CS] sorted values
-  int* count;        // [B, nb]
-  int* slot;         // [B, N]
-  int* binof;        // [B, N]
-  int* tmp;          // [B, N]
-  float* prec;       // [B, H, W, CP]
-  float* gpart;      // [B, groups]
+// Everything the kernel bodies need about ONE image of one problem: its
+// shape, its inputs/outputs and its slices of the saved state and workspace.
+// The view of image 0 plus image_of() gives every image of a batch.
+struct ImageView {
+  int N, C, H, W, T, nbx, nby, nb, CS, CP, per_point;
+  int npass, dbits, kbits, ntiles, units256;
+  int bx_blocks, by_blocks;
+  float radius, inv_tile;
+  // inputs / outputs
+  const float2* pos;        // [N]
+  const float* sigma;       // per point: [N]; shared: the image's one value
+  const float* values;      // [N, C]
+  float* out;               // [C, H, W]
+  const float* grad_out;    // [C, H, W]
+  float* grad_pos;          // [N, 2] or null
+  float* grad_sigma;        // per point [N]; shared: the image's one value; or null
+  float* grad_values;       // [N, C] or null
+  // saved state
+  float* Z;                 // [H, W]
+  float* reach;             // [1]
+  int* offset;              // [nb + 1]
+  int* perm;                // [N]
+  float4* geo;              // [N]
+  float* col;               // [N, CS]
+  // workspace
+  int* binof;               // [N] bin key of each point (point order)
+  int* keysF;               // [N] bin keys in sorted order
+  int* kA; int* vA; int* kB; int* vB;   // radix ping-pong buffers
+  int* hist;                // [256 * ntiles]
+  float* rpart;             // [units256] partial maxima of radius*sigma
+  float* prec;              // [H, W, CP] backward pixel records
+  float* gpart;             // [units256] partial sums of dL/dsigma (shared sigma)
 };
 
-inline Views make_views(const Layout& L, void* saved, void* work) {
-  char* s = static_cast<char*>(saved);
-  char* w = static_cast<char*>(work);
-  Views v;
-  v.Z = reinterpret_cast<float*>(s + L.Z);
-  v.reach = reinterpret_cast<float*>(s + L.reach);
-  v.offset = reinterpret_cast<int*>(s + L.offset);
-  v.perm = reinterpret_cast<int*>(s + L.perm);
-  v.geo = reinterpret_cast<float4*>(s + L.geo);
-  v.col = reinterpret_cast<float*>(s + L.col);
-  v.count = reinterpret_cast<int*>(w + L.count);
-  v.slot = reinterpret_cast<int*>(w + L.slot);
-  v.binof = reinterpret_cast<int*>(w + L.binof);
-  v.tmp = reinterpret_cast<int*>(w + L.tmp);
-  v.prec = reinterpret_cast<float*>(w + L.prec);
-  v.gpart = reinterpret_cast<float*>(w + L.gpart);
+template <typename T>
+__host__ __device__ inline T* shift(T* p, size_t n) { return p ? p + n : p; }
+
+// The view of image b, given the view of image 0 of the same problem.
+__host__ __device__ inline ImageView image_of(const ImageView& v0, int b) {
+  if (b == 0) return v0;
+  ImageView v = v0;
+  const size_t bb = b, N = v0.N, HW = size_t(v0.H) * v0.W;
+  v.pos = shift(v0.pos, bb * N);
+  v.sigma = shift(v0.sigma, v0.per_point ? bb * N : bb);
+  v.values = shift(v0.values, bb * N * v0.C);
+  v.out = shift(v0.out, bb * v0.C * HW);
+  v.grad_out = shift(v0.grad_out, bb * v0.C * HW);
+  v.grad_pos = shift(v0.grad_pos, bb * N * 2);
+  v.grad_sigma = shift(v0.grad_sigma, v0.per_point ? bb * N : bb);
+  v.grad_values = shift(v0.grad_values, bb * N * v0.C);
+  v.Z = shift(v0.Z, bb * HW);
+  v.reach = shift(v0.reach, bb);
+  v.offset = shift(v0.offset, bb * (size_t(v0.nb) + 1));
+  v.perm = shift(v0.perm, bb * N);
+  v.geo = shift(v0.geo, bb * N);
+  v.col = shift(v0.col, bb * N * v0.CS);
+  v.binof = shift(v0.binof, bb * N);
+  v.keysF = shift(v0.keysF, bb * N);
+  v.kA = shift(v0.kA, bb * N);
+  v.vA = shift(v0.vA, bb * N);
+  v.kB = shift(v0.kB, bb * N);
+  v.vB = shift(v0.vB, bb * N);
+  v.hist = shift(v0.hist, bb * 256 * size_t(v0.ntiles));
+  v.rpart = shift(v0.rpart, bb * v0.units256);
+  v.prec = shift(v0.prec, bb * HW * v0.CP);
+  v.gpart = shift(v0.gpart, bb * v0.units256);
   return v;
 }
 
-// Kernel launch entry points (defined in the kernel translation units).
-hipError_t launch_binning(const Geometry& g, const float* pos, const float* sigma,
-                          const float* values, const Views& v, hipStream_t st);
-hipError_t launch_forward(const Geometry& g, const Views& v, float* out, hipStream_t st);
-hipError_t launch_backward(const Geometry& g, const float* sigma, const float* out,
+// The view of image 0 of a validated problem.
+inline ImageView make_view(const Geometry& g, const Layout& L, void* saved, void* work,
+                           const float* pos, const float* sigma, const float* values, float* out,
                            const float* grad_out, float* grad_pos, float* grad_sigma,
-                           float* grad_values, const Views& v, hipStream_t st);
+                           float* grad_values) {
+  char* s = static_cast<char*>(saved);
+  char* w = static_cast<char*>(work);
+  ImageView v;
+  v.N = g.N; v.C = g.C; v.H = g.H; v.W = g.W; v.T = g.T; v.nbx = g.nbx; v.nby = g.nby; v.nb = g.nb;
+  v.CS = g.CS; v.CP = g.CP; v.per_point = g.per_point;
+  v.npass = g.npass; v.dbits = g.dbits; v.kbits = g.kbits; v.ntiles = g.ntiles;
+  v.units256 = g.units256;
+  v.bx_blocks = g.bx_blocks; v.by_blocks = g.by_blocks;
+  v.radius = g.radius;
+  v.inv_tile = 1.0f / (float)g.T;
+  v.pos = reinterpret_cast<const float2*>(pos);
+  v.sigma = sigma;
+  v.values = values;
+  v.out = out;
+  v.grad_out = grad_out;
+  v.grad_pos = grad_pos;
+  v.grad_sigma = grad_sigma;
+  v.grad_values = grad_values;
+  v.Z = s ? reinterpret_cast<float*>(s + L.Z) : nullptr;
+  v.reach = s ? reinterpret_cast<float*>(s + L.reach) : nullptr;
+  v.offset = s ? reinterpret_cast<int*>(s + L.offset) : nullptr;
+  v.perm = s ? reinterpret_cast<int*>(s + L.perm) : nullptr;
+  v.geo = s ? reinterpret_cast<float4*>(s + L.geo) : nullptr;
+  v.col = s ? reinterpret_cast<float*>(s + L.col) : nullptr;
+  v.binof = w ? reinterpret_cast<int*>(w + L.binof) : nullptr;
+  v.keysF = w ? reinterpret_cast<int*>(w + L.keysF) : nullptr;
+  v.kA = w ? reinterpret_cast<int*>(w + L.kA) : nullptr;
+  v.vA = w ? reinterpret_cast<int*>(w + L.vA) : nullptr;
+  v.kB = w ? reinterpret_cast<int*>(w + L.kB) : nullptr;
+  v.vB = w ? reinterpret_cast<int*>(w + L.vB) : nullptr;
+  v.hist = w ? reinterpret_cast<int*>(w + L.hist) : nullptr;
+  v.rpart = w ? reinterpret_cast<float*>(w + L.rpart) : nullptr;
+  v.prec = w ? reinterpret_cast<float*>(w + L.prec) : nullptr;
+  v.gpart = w ? reinterpret_cast<float*>(w + L.gpart) : nullptr;
+  return v;
+}
+
+// Optional per-kernel event timing (enabled by interp_profile_enable): the
+// constructor records a start event on `st`, the destructor a stop event.
+struct ProfRange {
+  ProfRange(const char* name, hipStream_t st);
+  ~ProfRange();
+  int token;
+  hipStream_t st;
+};
+
+// Host launchers of the single-call path (single.hip).
+hipError_t launch_forward_all(const Geometry& g, const ImageView& v0, hipStream_t st);
+hipError_t launch_backward_all(const Geometry& g, const ImageView& v0, hipStream_t st);
+hipError_t launch_debug_count(const Geometry& g, const ImageView& v0, int* count, hipStream_t st);
 
 }  // namespace gmm

@@ -1,0 +1,492 @@
+// Kernel bodies of the Gaussian-mixture interpolation, as device functions on
+// one ImageView.  The single-call path (single.hip) and the serving job-table
+// path (server.hip) wrap the same functions, so a request computes exactly
+// the same bits alone and inside a batch.
+//
+// Method (paper, Section 2, Eq. 1 and Eq. 2): out_i = sum_j w_ij c_j / Z_i,
+// Z_i = sum_j w_ij, w_ij = exp(-|g_i - p_j|^2 / (2 sigma_j^2)), summed over the
+// points close enough to pixel i (radius * sigma_j, inclusive, float32 test
+// without FMA); every channel on its own.
+//
+// Phases of one forward:
+//   bin_keys       bin key of every point; partial maxima of radius*sigma
+//   radix_hist / radix_scan / radix_scatter   (x npass)
+//                  stable LSD radix sort of (key, point index) -> the
+//                  counting-sort order by bin, ties by point index
+//   bin_finish     bin offsets from the sorted keys; per-image reach
+//   bin_gather     sorted point records (x, y, k, R2) and values
+//   forward        the gather: per 8x8 pixel block, candidates from the bins
+//                  within reach, culled per wavefront, hits evaluated per pixel
+// Backward (quotient rule on Eq. 1; formulas in include/gmminterp.h):
+//   bwd_pixel      G'_ik = G_ik / Z_i and beta_i per pixel
+//   bwd_point      per point: walk its disk's bounding box, recompute w_ij,
+//                  accumulate the gradients in registers (no atomics)
+//   bwd_sigma_sum  shared sigma: fixed-order sum of the per-point dL/dsigma
+#pragma once
+
+#include <climits>
+
+#include "common.hpp"
+
+namespace gmm {
+namespace dev {
+
+constexpr float kLog2e = 1.4426950408889634f;
+
+__device__ inline int bin_coord(float c, float inv_tile, int nmax) {
+  // floor(c / tile) clamped to [0, nmax-1]; c * (1/tile) is exact for a
+  // power-of-two tile.  NaN and negative values land in bin 0.
+  const float f = floorf(c * inv_tile);
+  if (!(f >= 0.0f)) return 0;
+  if (f >= (float)(nmax - 1)) return nmax - 1;
+  return (int)f;
+}
+
+__device__ inline float sigma_of(const ImageView& v, int j) {
+  return v.per_point ? v.sigma[j] : v.sigma[0];
+}
+
+// The sorted point record: x, y, exp2 scale k = -log2(e)/(2 sigma^2) and the
+// squared radius R2 = f32(f32(radius*sigma)^2) of the radius test.
+__device__ inline float4 make_geo(float2 p, float sg, float radius) {
+  const float rs = __fmul_rn(radius, sg);
+  const float R2 = __fmul_rn(rs, rs);
+  const float kk = -0.5f * kLog2e / __fmul_rn(sg, sg);
+  return make_float4(p.x, p.y, kk, R2);
+}
+
+// Conservative reach (pixels) of a point set whose largest radius*sigma is
+// rs: covers the float32 rounding of the radius test and of the bin bounds.
+__device__ inline float conservative_reach(float rs) { return rs * (1.0f + 0x1p-10f) + 0x1p-6f; }
+
+__device__ inline float block_max(float x, float* red4) {
+  for (int o = 32; o > 0; o >>= 1) x = fmaxf(x, __shfl_xor(x, o));
+  if ((threadIdx.x & 63) == 0) red4[threadIdx.x >> 6] = x;
+  __syncthreads();
+  const float m = fmaxf(fmaxf(red4[0], red4[1]), fmaxf(red4[2], red4[3]));
+  __syncthreads();
+  return m;
+}
+
+// Fixed-order sum over a 256-thread block (xor tree, then the four waves in order).
+__device__ inline float block_sum(float x, float* red4) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  if ((threadIdx.x & 63) == 0) red4[threadIdx.x >> 6] = x;
+  __syncthreads();
+  const float s = (red4[0] + red4[1]) + (red4[2] + red4[3]);
+  __syncthreads();
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// Binning: stable LSD radix sort of the bin keys (no global atomics)
+// ---------------------------------------------------------------------------
+
+// unit = 256 points (block of 256 threads)
+__device__ inline void bin_keys(const ImageView& v, int unit, float* red4) {
+  const int j = unit * 256 + threadIdx.x;
+  float rs = 0.0f;
+  if (j < v.N) {
+    const float2 p = v.pos[j];
+    const int key = bin_coord(p.y, v.inv_tile, v.nby) * v.nbx + bin_coord(p.x, v.inv_tile, v.nbx);
+    v.binof[j] = key;
+    if (v.npass == 0) {  // a single bin: the identity order is already sorted
+      v.keysF[j] = key;
+      v.perm[j] = j;
+    }
+    rs = __fmul_rn(v.radius, sigma_of(v, j));
+    if (!(rs >= 0.0f)) rs = 0.0f;  // caller contract violated; keep the reach sane
+  }
+  const float m = block_max(rs, red4);
+  if (threadIdx.x == 0) v.rpart[unit] = m;
+}
+
+__device__ inline void radix_pass_bits(const ImageView& v, int p, int* shift, int* width) {
+  *shift = p * v.dbits;
+  *width = min(v.dbits, v.kbits - *shift);
+}
+
+// unit = one tile of kRadixTile keys: digit histogram of the tile
+__device__ inline void radix_hist(const ImageView& v, int p, int tile, int* lh) {
+  int shift, width;
+  radix_pass_bits(v, p, &shift, &width);
+  const int ndig = 1 << width, mask = ndig - 1;
+  const int* kin = p == 0 ? v.binof : (((p - 1) & 1) == 0 ? v.kA : v.kB);
+  lh[threadIdx.x] = 0;
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRadixItems; ++r) {
+    const int idx = tile * kRadixTile + r * 256 + threadIdx.x;
+    if (idx < v.N) atomicAdd(&lh[(kin[idx] >> shift) & mask], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < ndig) v.hist[threadIdx.x * v.ntiles + tile] = lh[threadIdx.x];
+  __syncthreads();
+}
+
+// one 1024-thread block per image: exclusive scan of hist in digit-major order
+__device__ inline void radix_scan(const ImageView& v, int p, int* wsum, int* carry_s) {
+  int shift, width;
+  radix_pass_bits(v, p, &shift, &width);
+  const int n = (1 << width) * v.ntiles;
+  int* h = v.hist;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  int carry = 0;
+  for (int base = 0; base < n; base += 4096) {
+    int x[4];
+    const int i0 = base + tid * 4;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) x[q] = (i0 + q < n) ? h[i0 + q] : 0;
+    const int local = x[0] + x[1] + x[2] + x[3];
+    int incl = local;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int t = __shfl_up(incl, d);
+      if (lane >= d) incl += t;
+    }
+    if (lane == 63) wsum[wid] = incl;
+    __syncthreads();
+    if (wid == 0) {
+      const int s = lane < 16 ? wsum[lane] : 0;
+      int si = s;
+#pragma unroll
+      for (int d = 1; d < 16; d <<= 1) {
+        const int t = __shfl_up(si, d);
+        if (lane >= d) si += t;
+      }
+      if (lane < 16) wsum[lane] = si - s;  // exclusive prefix of the wave sums
+      if (lane == 15) *carry_s = si;       // total of this stretch
+    }
+    __syncthreads();
+    int run = carry + wsum[wid] + incl - local;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (i0 + q < n) h[i0 + q] = run;
+      run += x[q];
+    }
+    carry += *carry_s;
+    __syncthreads();
+  }
+}
+
+// unit = one tile: stable scatter of (key, value) by the pass's digit.  Keys
+// are processed in rounds of 256 in index order; within a round, a
+// wavefront ranks equal digits by ballot (multisplit), and the wavefronts
+// are ordered by their index, so equal digits keep their input order.
+__device__ inline void radix_scatter(const ImageView& v, int p, int tile, int* wcnt /*[4][256]*/,
+                                     int* run /*[256]*/, int* base /*[256]*/) {
+  int shift, width;
+  radix_pass_bits(v, p, &shift, &width);
+  const int ndig = 1 << width, mask = ndig - 1;
+  const int* kin = p == 0 ? v.binof : (((p - 1) & 1) == 0 ? v.kA : v.kB);
+  const int* vin = p == 0 ? nullptr : (((p - 1) & 1) == 0 ? v.vA : v.vB);
+  const bool last = p == v.npass - 1;
+  int* kout = last ? v.keysF : ((p & 1) == 0 ? v.kA : v.kB);
+  int* vout = last ? v.perm : ((p & 1) == 0 ? v.vA : v.vB);
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  run[t] = 0;
+  base[t] = t < ndig ? v.hist[t * v.ntiles + tile] : 0;
+  wcnt[t] = 0; wcnt[256 + t] = 0; wcnt[512 + t] = 0; wcnt[768 + t] = 0;
+  __syncthreads();
+  const unsigned long long below = (1ull << lane) - 1ull;
+  for (int r = 0; r < kRadixItems; ++r) {
+    const int idx = tile * kRadixTile + r * 256 + t;
+    const bool valid = idx < v.N;
+    const int key = valid ? kin[idx] : 0;
+    const int val = valid ? (vin ? vin[idx] : idx) : 0;
+    const int d = (key >> shift) & mask;
+    unsigned long long peers = __ballot(valid);
+    for (int bit = 0; bit < width; ++bit) {
+      const bool on = (d >> bit) & 1;
+      const unsigned long long m = __ballot(on);
+      peers &= on ? m : ~m;
+    }
+    const int rank = __popcll(peers & below);
+    if (valid && rank == 0) wcnt[wid * 256 + d] = __popcll(peers);
+    __syncthreads();
+    if (valid) {
+      int off = base[d] + run[d] + rank;
+      for (int w = 0; w < wid; ++w) off += wcnt[w * 256 + d];
+      kout[off] = key;
+      vout[off] = val;
+    }
+    __syncthreads();
+    if (t < ndig) {
+      run[t] += wcnt[t] + wcnt[256 + t] + wcnt[512 + t] + wcnt[768 + t];
+      wcnt[t] = 0; wcnt[256 + t] = 0; wcnt[512 + t] = 0; wcnt[768 + t] = 0;
+    }
+    __syncthreads();
+  }
+}
+
+// unit = 256 sorted positions (N + 1 positions in all): bin offsets from the
+// sorted keys -- position i opens every bin in (key[i-1], key[i]]; position N
+// closes the rest.  Unit 0 also reduces the per-image reach.
+__device__ inline void bin_finish(const ImageView& v, int unit, float* red4) {
+  const int i = unit * 256 + threadIdx.x;
+  if (i <= v.N) {
+    const int kcur = i < v.N ? v.keysF[i] : v.nb;
+    const int kprev = i > 0 ? v.keysF[i - 1] : -1;
+    for (int k = kprev + 1; k <= kcur; ++k) v.offset[k] = i;
+  }
+  if (unit == 0) {
+    float m = 0.0f;
+    for (int q = threadIdx.x; q < v.units256; q += 256) m = fmaxf(m, v.rpart[q]);
+    m = block_max(m, red4);
+    if (threadIdx.x == 0) v.reach[0] = m;
+  }
+}
+
+// unit = 256 sorted positions: gather the sorted records and values
+__device__ inline void bin_gather(const ImageView& v, int unit) {
+  const int i = unit * 256 + threadIdx.x;
+  if (i >= v.N) return;
+  const int j = v.perm[i];
+  v.geo[i] = make_geo(v.pos[j], sigma_of(v, j), v.radius);
+  const float* src = v.values + (size_t)j * v.C;
+  float* dst = v.col + (size_t)i * v.CS;
+  for (int c = 0; c < v.CS; c += 4) {
+    float4 q;
+    q.x = c < v.C ? src[c] : 0.0f;
+    q.y = c + 1 < v.C ? src[c + 1] : 0.0f;
+    q.z = c + 2 < v.C ? src[c + 2] : 0.0f;
+    q.w = c + 3 < v.C ? src[c + 3] : 0.0f;
+    *reinterpret_cast<float4*>(dst + c) = q;
+  }
+}
+
+// number of positions bin_finish covers, in units of 256
+__host__ __device__ inline int finish_units(int N) { return (N + 1 + 255) / 256; }
+
+// ---------------------------------------------------------------------------
+// Forward gather
+// ---------------------------------------------------------------------------
+
+// Orders one wavefront's LDS writes before its lanes read each other's data.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__host__ __device__ inline int fwd_tiles_x(int bx_blocks) { return (bx_blocks + 1) / 2; }
+__host__ __device__ inline int fwd_tiles(int bx_blocks, int by_blocks) {
+  return ((bx_blocks + 1) / 2) * ((by_blocks + 1) / 2);
+}
+
+// One 256-thread block = one 16x16 pixel tile; wavefront w owns the 8x8
+// block (w & 1, w >> 1) of it, one pixel per lane.  Candidates are the
+// records of the bins within reach of the block (one contiguous range per
+// bin row), taken 64 at a time: each lane tests one candidate's disk against
+// the block, the hits are compacted in candidate order into the wavefront's
+// LDS list, and every lane then evaluates each hit for its pixel.
+template <int CT>
+__device__ inline void forward_tile(const ImageView& v, int tile, float4* s_geo /*[4][64]*/,
+                                    float4* s_col /*[4][64*CS/4]*/) {
+  constexpr int CS = CT < 4 ? 4 : CT;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int wgx = fwd_tiles_x(v.bx_blocks);
+  const int ty = tile / wgx, tx = tile - ty * wgx;
+  const int u0 = (2 * tx + (wid & 1)) * kBlockSide;
+  const int v0 = (2 * ty + (wid >> 1)) * kBlockSide;
+  if (u0 >= v.W || v0 >= v.H) return;
+  const int ue = min(u0 + kBlockSide - 1, v.W - 1);
+  const int ve = min(v0 + kBlockSide - 1, v.H - 1);
+  const int u = u0 + (lane & 7), vv = v0 + (lane >> 3);
+  const float fu = (float)u, fv = (float)vv;
+
+  // float math runs on the vector ALU; readfirstlane keeps the wave-uniform
+  // loop bounds in scalar registers
+  const float Rh = conservative_reach(v.reach[0]);
+  const int bx_lo = __builtin_amdgcn_readfirstlane(bin_coord((float)u0 - Rh, v.inv_tile, v.nbx));
+  const int bx_hi = __builtin_amdgcn_readfirstlane(bin_coord((float)ue + Rh, v.inv_tile, v.nbx));
+  const int by_lo = __builtin_amdgcn_readfirstlane(bin_coord((float)v0 - Rh, v.inv_tile, v.nby));
+  const int by_hi = __builtin_amdgcn_readfirstlane(bin_coord((float)ve + Rh, v.inv_tile, v.nby));
+  const float4* gb = v.geo;
+  const float* cb = v.col;
+
+  float Z = 0.0f;
+  float acc[CT];
+#pragma unroll
+  for (int k = 0; k < CT; ++k) acc[k] = 0.0f;
+
+  float4* lgeo = s_geo + wid * 64;
+  float4* lcol = s_col + wid * 64 * (CS / 4);
+
+  for (int by = by_lo; by <= by_hi; ++by) {
+    const int s = __builtin_amdgcn_readfirstlane(v.offset[by * v.nbx + bx_lo]);
+    const int e = __builtin_amdgcn_readfirstlane(v.offset[by * v.nbx + bx_hi + 1]);
+    for (int c0 = s; c0 < e; c0 += 64) {
+      const int jc = c0 + lane;
+      bool hit = false;
+      float4 g = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (jc < e) {
+        g = gb[jc];
+        const float ex = fmaxf(fmaxf((float)u0 - g.x, g.x - (float)ue), 0.0f);
+        const float ey = fmaxf(fmaxf((float)v0 - g.y, g.y - (float)ve), 0.0f);
+        hit = ex * ex + ey * ey <= g.w * 1.001f + 1e-6f;
+      }
+      const unsigned long long mask = __ballot(hit);
+      if (mask == 0) continue;
+      if (hit) {
+        const int slot = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                                   __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0));
+        lgeo[slot] = g;
+        const float4* cp = reinterpret_cast<const float4*>(cb + (size_t)jc * CS);
+#pragma unroll
+        for (int q = 0; q < CS / 4; ++q) lcol[slot * (CS / 4) + q] = cp[q];
+      }
+      wave_lds_sync();
+      const int nh = __popcll(mask);
+      for (int i = 0; i < nh; ++i) {
+        const float4 r = lgeo[i];
+        float cc[CS];
+#pragma unroll
+        for (int q = 0; q < CS / 4; ++q) {
+          const float4 tq = lcol[i * (CS / 4) + q];
+          cc[4 * q] = tq.x; cc[4 * q + 1] = tq.y; cc[4 * q + 2] = tq.z; cc[4 * q + 3] = tq.w;
+        }
+        // radius test exactly as specified: float32, every operation rounded
+        const float dx = fu - r.x;
+        const float dy = fv - r.y;
+        const float d2 = dx * dx + dy * dy;
+        float w = __builtin_amdgcn_exp2f(d2 * r.z);
+        w = (d2 <= r.w) ? w : 0.0f;
+        Z += w;
+#pragma unroll
+        for (int k = 0; k < CT; ++k) acc[k] = __builtin_fmaf(w, cc[k], acc[k]);
+      }
+      wave_lds_sync();
+    }
+  }
+
+  if (u <= ue && vv <= ve) {
+    const size_t HW = (size_t)v.H * v.W;
+    const size_t pix = (size_t)vv * v.W + u;
+#pragma unroll
+    for (int k = 0; k < CT; ++k) {
+      if (k < v.C) v.out[k * HW + pix] = Z > 0.0f ? acc[k] / Z : 0.0f;
+    }
+    v.Z[pix] = Z;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Backward
+// ---------------------------------------------------------------------------
+
+// unit = 256 pixels: G'_ik = G_ik / Z_i and beta_i = sum_k G_ik out_ik / Z_i,
+// packed per pixel as (G'_0 .. G'_{CT-1}, beta, zero padding)
+template <int CT>
+__device__ inline void bwd_pixel(const ImageView& v, int unit) {
+  constexpr int CP = (CT + 1 + 3) / 4 * 4;
+  const int HW = v.H * v.W;
+  const int i = unit * 256 + threadIdx.x;
+  if (i >= HW) return;
+  const float z = v.Z[i];
+  float rec[CP];
+#pragma unroll
+  for (int k = 0; k < CP; ++k) rec[k] = 0.0f;
+  if (z > 0.0f) {
+    const float a = 1.0f / z;
+    float beta = 0.0f;
+#pragma unroll
+    for (int k = 0; k < CT; ++k) {
+      if (k < v.C) {
+        const size_t idx = (size_t)k * HW + i;
+        const float gk = v.grad_out[idx];
+        rec[k] = gk * a;
+        beta = __builtin_fmaf(gk, v.out[idx], beta);
+      }
+    }
+    rec[CT] = beta * a;
+  }
+  float4* dst = reinterpret_cast<float4*>(v.prec + (size_t)i * CP);
+#pragma unroll
+  for (int q = 0; q < CP / 4; ++q)
+    dst[q] = make_float4(rec[4 * q], rec[4 * q + 1], rec[4 * q + 2], rec[4 * q + 3]);
+}
+
+// unit = 256 points in sorted order.  Each thread walks its point's disk
+// bounding box, repeats the forward's radius test bit for bit, recomputes
+// w_ij and accumulates in registers; results go to the point's own index.
+template <int CT>
+__device__ inline void bwd_point(const ImageView& v, int unit, float* red4) {
+  constexpr int CS = CT < 4 ? 4 : CT;
+  constexpr int CP = (CT + 1 + 3) / 4 * 4;
+  const int t = unit * 256 + threadIdx.x;
+  float gsig = 0.0f;
+  if (t < v.N) {
+    const float4 g = v.geo[t];
+    float cc[CT];
+#pragma unroll
+    for (int k = 0; k < CT; ++k) cc[k] = v.col[(size_t)t * CS + k];
+    const int j = v.perm[t];
+    const float sg = sigma_of(v, j);
+    const float Rh = conservative_reach(__fmul_rn(v.radius, sg));
+    // bounding box of the disk, clipped to the image (the float clamps also
+    // drop NaN and keep the conversions in range)
+    const float fulo = fminf(fmaxf(ceilf(g.x - Rh), 0.0f), (float)v.W);
+    const float fuhi = fmaxf(fminf(floorf(g.x + Rh), (float)(v.W - 1)), -1.0f);
+    const float fvlo = fminf(fmaxf(ceilf(g.y - Rh), 0.0f), (float)v.H);
+    const float fvhi = fmaxf(fminf(floorf(g.y + Rh), (float)(v.H - 1)), -1.0f);
+    const int ulo = (int)fulo, uhi = (int)fuhi, vlo = (int)fvlo, vhi = (int)fvhi;
+    float gx = 0.0f, gy = 0.0f, gs = 0.0f;
+    float gc[CT];
+#pragma unroll
+    for (int k = 0; k < CT; ++k) gc[k] = 0.0f;
+    for (int py = vlo; py <= vhi; ++py) {
+      const float dy = (float)py - g.y;
+      const float dyy = dy * dy;
+      const float* prow = v.prec + (size_t)py * v.W * CP;
+      for (int px = ulo; px <= uhi; ++px) {
+        const float dx = (float)px - g.x;
+        const float d2 = dx * dx + dyy;
+        if (d2 <= g.w) {
+          const float w = __builtin_amdgcn_exp2f(d2 * g.z);
+          const float4* rp = reinterpret_cast<const float4*>(prow + (size_t)px * CP);
+          float rec[CP];
+#pragma unroll
+          for (int q = 0; q < CP / 4; ++q) {
+            const float4 r4 = rp[q];
+            rec[4 * q] = r4.x; rec[4 * q + 1] = r4.y; rec[4 * q + 2] = r4.z; rec[4 * q + 3] = r4.w;
+          }
+          float A = -rec[CT];
+#pragma unroll
+          for (int k = 0; k < CT; ++k) {
+            A = __builtin_fmaf(rec[k], cc[k], A);
+            gc[k] = __builtin_fmaf(w, rec[k], gc[k]);
+          }
+          const float tA = A * w;
+          gx = __builtin_fmaf(tA, dx, gx);
+          gy = __builtin_fmaf(tA, dy, gy);
+          gs = __builtin_fmaf(tA, d2, gs);
+        }
+      }
+    }
+    const float inv_s2 = 1.0f / (sg * sg);
+    if (v.grad_pos) reinterpret_cast<float2*>(v.grad_pos)[j] = make_float2(gx * inv_s2, gy * inv_s2);
+    gsig = gs * inv_s2 / sg;
+    if (v.grad_sigma && v.per_point) v.grad_sigma[j] = gsig;
+    if (v.grad_values) {
+#pragma unroll
+      for (int k = 0; k < CT; ++k)
+        if (k < v.C) v.grad_values[(size_t)j * v.C + k] = gc[k];
+    }
+  }
+  if (!v.per_point && v.grad_sigma) {
+    const float s = block_sum(gsig, red4);
+    if (threadIdx.x == 0) v.gpart[unit] = s;
+  }
+}
+
+// one 256-thread block per image: grad_sigma = fixed-order sum of gpart
+__device__ inline void bwd_sigma_sum(const ImageView& v, float* red4) {
+  float s = 0.0f;
+  for (int q = threadIdx.x; q < v.units256; q += 256) s += v.gpart[q];
+  s = block_sum(s, red4);
+  if (threadIdx.x == 0) v.grad_sigma[0] = s;
+}
+
+}  // namespace dev
+}  // namespace gmm

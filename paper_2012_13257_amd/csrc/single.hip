@@ -1,0 +1,177 @@
+// Single-call path: one launch per phase over every image of one problem
+// (grid.y = image, or a flattened XCD-aware grid for the forward gather).
+#include "kernels.hpp"
+
+namespace gmm {
+namespace {
+
+__global__ __launch_bounds__(256) void k_bin_keys(ImageView v0) {
+  __shared__ float red4[4];
+  dev::bin_keys(image_of(v0, blockIdx.y), blockIdx.x, red4);
+}
+
+__global__ __launch_bounds__(256) void k_radix_hist(ImageView v0, int p) {
+  __shared__ int lh[256];
+  dev::radix_hist(image_of(v0, blockIdx.y), p, blockIdx.x, lh);
+}
+
+__global__ __launch_bounds__(1024) void k_radix_scan(ImageView v0, int p) {
+  __shared__ int wsum[16];
+  __shared__ int carry;
+  dev::radix_scan(image_of(v0, blockIdx.x), p, wsum, &carry);
+}
+
+__global__ __launch_bounds__(256) void k_radix_scatter(ImageView v0, int p) {
+  __shared__ int wcnt[4 * 256];
+  __shared__ int run[256];
+  __shared__ int base[256];
+  dev::radix_scatter(image_of(v0, blockIdx.y), p, blockIdx.x, wcnt, run, base);
+}
+
+__global__ __launch_bounds__(256) void k_bin_finish(ImageView v0) {
+  __shared__ float red4[4];
+  dev::bin_finish(image_of(v0, blockIdx.y), blockIdx.x, red4);
+}
+
+__global__ __launch_bounds__(256) void k_bin_gather(ImageView v0) {
+  dev::bin_gather(image_of(v0, blockIdx.y), blockIdx.x);
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs; give every XCD a
+// contiguous range of tiles so that neighbouring tiles (which read the same
+// halo records) share one L2.
+__device__ inline int xcd_remap(int bid, int nblocks) {
+  const int xcd = bid & 7, idx = bid >> 3;
+  const int per = nblocks >> 3, rem = nblocks & 7;
+  return xcd * per + min(xcd, rem) + idx;
+}
+
+template <int CT>
+__global__ __launch_bounds__(256) void k_forward(ImageView v0, int tiles_per_image, int total) {
+  constexpr int CS = CT < 4 ? 4 : CT;
+  __shared__ float4 s_geo[4 * 64];
+  __shared__ float4 s_col[4 * 64 * (CS / 4)];
+  const int t = xcd_remap(blockIdx.x, total);
+  const int b = t / tiles_per_image;
+  dev::forward_tile<CT>(image_of(v0, b), t - b * tiles_per_image, s_geo, s_col);
+}
+
+template <int CT>
+__global__ __launch_bounds__(256) void k_bwd_pixel(ImageView v0) {
+  dev::bwd_pixel<CT>(image_of(v0, blockIdx.y), blockIdx.x);
+}
+
+template <int CT>
+__global__ __launch_bounds__(256) void k_bwd_point(ImageView v0) {
+  __shared__ float red4[4];
+  dev::bwd_point<CT>(image_of(v0, blockIdx.y), blockIdx.x, red4);
+}
+
+__global__ __launch_bounds__(256) void k_bwd_sigma_sum(ImageView v0) {
+  __shared__ float red4[4];
+  dev::bwd_sigma_sum(image_of(v0, blockIdx.x), red4);
+}
+
+__global__ __launch_bounds__(256) void k_debug_count(ImageView v0, int* count) {
+  const ImageView v = image_of(v0, blockIdx.y);
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k < v.nb) count[(size_t)blockIdx.y * v.nb + k] = v.offset[k + 1] - v.offset[k];
+}
+
+inline unsigned cdiv(long long n, int d) { return (unsigned)((n + d - 1) / d); }
+
+template <int CT>
+hipError_t launch_forward_t(const Geometry& g, const ImageView& v0, hipStream_t st) {
+  const int per = dev::fwd_tiles(g.bx_blocks, g.by_blocks);
+  const long long total = (long long)per * g.B;
+  if (total >= (1LL << 31)) return hipErrorInvalidValue;
+  ProfRange pr_("forward", st);
+  hipLaunchKernelGGL(k_forward<CT>, dim3((unsigned)total), dim3(256), 0, st, v0, per, (int)total);
+  return hipSuccess;
+}
+
+template <int CT>
+hipError_t launch_backward_t(const Geometry& g, const ImageView& v0, hipStream_t st) {
+  {
+    ProfRange pr_("bwd_pixel", st);
+    hipLaunchKernelGGL(k_bwd_pixel<CT>, dim3(cdiv((long long)g.H * g.W, 256), g.B), dim3(256), 0,
+                       st, v0);
+  }
+  if (g.N > 0) {
+    ProfRange pr_("bwd_point", st);
+    hipLaunchKernelGGL(k_bwd_point<CT>, dim3(g.units256, g.B), dim3(256), 0, st, v0);
+  }
+  if (!g.per_point && v0.grad_sigma) {
+    ProfRange pr_("bwd_sigma_sum", st);
+    hipLaunchKernelGGL(k_bwd_sigma_sum, dim3(g.B), dim3(256), 0, st, v0);
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_forward_all(const Geometry& g, const ImageView& v0, hipStream_t st) {
+  if (g.N > 0) {
+    ProfRange pr_("bin_keys", st);
+    hipLaunchKernelGGL(k_bin_keys, dim3(g.units256, g.B), dim3(256), 0, st, v0);
+  }
+  for (int p = 0; p < g.npass && g.N > 0; ++p) {
+    {
+      ProfRange pr_("radix_hist", st);
+      hipLaunchKernelGGL(k_radix_hist, dim3(g.ntiles, g.B), dim3(256), 0, st, v0, p);
+    }
+    {
+      ProfRange pr_("radix_scan", st);
+      hipLaunchKernelGGL(k_radix_scan, dim3(g.B), dim3(1024), 0, st, v0, p);
+    }
+    {
+      ProfRange pr_("radix_scatter", st);
+      hipLaunchKernelGGL(k_radix_scatter, dim3(g.ntiles, g.B), dim3(256), 0, st, v0, p);
+    }
+  }
+  {
+    ProfRange pr_("bin_finish", st);
+    hipLaunchKernelGGL(k_bin_finish, dim3(dev::finish_units(g.N), g.B), dim3(256), 0, st, v0);
+  }
+  if (g.N > 0) {
+    ProfRange pr_("bin_gather", st);
+    hipLaunchKernelGGL(k_bin_gather, dim3(g.units256, g.B), dim3(256), 0, st, v0);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  switch (g.CT) {
+    case 1: e = launch_forward_t<1>(g, v0, st); break;
+    case 2: e = launch_forward_t<2>(g, v0, st); break;
+    case 3: e = launch_forward_t<3>(g, v0, st); break;
+    case 4: e = launch_forward_t<4>(g, v0, st); break;
+    case 8: e = launch_forward_t<8>(g, v0, st); break;
+    case 16: e = launch_forward_t<16>(g, v0, st); break;
+    case 32: e = launch_forward_t<32>(g, v0, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_backward_all(const Geometry& g, const ImageView& v0, hipStream_t st) {
+  hipError_t e;
+  switch (g.CT) {
+    case 1: e = launch_backward_t<1>(g, v0, st); break;
+    case 2: e = launch_backward_t<2>(g, v0, st); break;
+    case 3: e = launch_backward_t<3>(g, v0, st); break;
+    case 4: e = launch_backward_t<4>(g, v0, st); break;
+    case 8: e = launch_backward_t<8>(g, v0, st); break;
+    case 16: e = launch_backward_t<16>(g, v0, st); break;
+    case 32: e = launch_backward_t<32>(g, v0, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_debug_count(const Geometry& g, const ImageView& v0, int* count, hipStream_t st) {
+  hipLaunchKernelGGL(k_debug_count, dim3(cdiv(g.nb, 256), g.B), dim3(256), 0, st, v0, count);
+  return hipGetLastError();
+}
+
+}  // namespace gmm

@@ -92,3 +92,18 @@ def test_forward_rejects_bad_arguments_on_host(L):
     rc = L.interp_backward(ctypes.byref(p), fake, fake, fake, None, fake, s, fake, None, None, None,
                            fake, w, None)
     assert rc == INTERP_EINVAL
+
+
+def test_bench_pair_count_matches_oracle():
+    """The roofline's work unit (pairs inside the radius) equals the oracle's brute force."""
+    import bench
+    import oracle
+    from paper_2012_13257_amd import synth
+    for seed in range(2):
+        wl = synth.random_workload(seed, 2, 400, 27, 35, sigma=(0.3, 2.5), blob_frac=0.5,
+                                   blob_std=(2, 6))
+        a = bench.pair_count(wl.pos, wl.sigma, wl.H, wl.W, 3.0)
+        b = sum(oracle.pair_count(wl.pos, wl.sigma, wl.H, wl.W, 3.0, b=k) for k in range(2))
+        assert a == b
+    wl = synth.random_workload(9, 1, 300, 20, 20, sigma=0.9)
+    assert bench.pair_count(wl.pos, wl.sigma, 20, 20, 3.0) == oracle.pair_count(wl.pos, wl.sigma, 20, 20, 3.0)
