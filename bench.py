@@ -137,6 +137,122 @@ def cpu_baseline(wl, G, budget_s: float):
             "fwd_mpix_s": 1.0 / t_fwd / 1e6}
 
 
+def serving_benchmark(log, n_requests: int = 4096, seed: int = 1004, budget_gb: float = 24.0,
+                      slots: int = 256):
+    """Serving stream (sides 64..1024, N = side^2 * U(0.25, 1), C in {1,3,4},
+    shared sigma U(0.5, 1.5), 30% with backward): the batching server against
+    one launch sequence per request on the same GPU, saturated and with
+    Poisson arrivals at 0.8x the baseline's saturated request rate."""
+    import ctypes
+    import torch
+    from paper_2012_13257_amd import _lib, interp, synth
+    from paper_2012_13257_amd.server import Server
+
+    trace = synth.config4_trace(n_requests, None, seed=seed)
+    gen = torch.Generator(device="cuda")
+    reqs = []
+    for r in trace:
+        gen.manual_seed(r.seed)
+        pos = torch.rand((1, r.N, 2), generator=gen, device="cuda") * r.side
+        pos.clamp_(max=float(np.nextafter(np.float32(r.side), np.float32(0))))
+        val = torch.rand((1, r.N, r.C), generator=gen, device="cuda")
+        sig = torch.full((1,), r.sigma, device="cuda")
+        G = torch.randn((1, r.C, r.side, r.side), generator=gen, device="cuda") if r.backward else None
+        prob = interp.problem(pos, sig, val, r.side, r.side, 3.0)
+        out = torch.empty((1, r.C, r.side, r.side), device="cuda")
+        grads = (torch.empty_like(pos), torch.empty_like(sig), torch.empty_like(val)) if r.backward else None
+        reqs.append(dict(r=r, pos=pos, sig=sig, val=val, G=G, prob=prob, out=out, grads=grads))
+    torch.cuda.synchronize()
+    px = np.array([q["r"].side ** 2 for q in reqs], dtype=np.float64)
+    total_px = float(px.sum())
+    log(f"serving: {n_requests} requests, {total_px / 1e6:.1f} Mpix, "
+        f"{sum(q['r'].backward for q in reqs)} with backward")
+
+    # --- one launch sequence per request (single-call API, one stream) ---
+    L = _lib.lib()
+    big = max(reqs, key=lambda q: q["r"].side ** 2 * 8 + q["r"].N)["prob"]
+    sb = max(L.interp_saved_bytes(ctypes.byref(q["prob"])) for q in reqs)
+    wb = max(L.interp_workspace_bytes(ctypes.byref(q["prob"])) for q in reqs)
+    del big
+    sbuf, saddr = interp.aligned_buffer(sb, "cuda")
+    wbuf, waddr = interp.aligned_buffer(wb, "cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def launch_one(q):
+        pb = ctypes.byref(q["prob"])
+        _lib.check("interp_forward", L.interp_forward(
+            pb, q["pos"].data_ptr(), q["sig"].data_ptr(), q["val"].data_ptr(), q["out"].data_ptr(),
+            saddr, sb, waddr, wb, stream))
+        if q["G"] is not None:
+            gp, gs, gv = q["grads"]
+            _lib.check("interp_backward", L.interp_backward(
+                pb, q["pos"].data_ptr(), q["sig"].data_ptr(), q["val"].data_ptr(),
+                q["out"].data_ptr(), saddr, sb, q["G"].data_ptr(), gp.data_ptr(), gs.data_ptr(),
+                gv.data_ptr(), waddr, wb, stream))
+
+    def baseline(arrivals):
+        evs = [torch.cuda.Event(enable_timing=True) for _ in reqs]
+        start = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        start.record()
+        for q, a, e in zip(reqs, arrivals, evs):
+            while time.perf_counter() - t0 < a:
+                pass
+            launch_one(q)
+            e.record()
+        torch.cuda.synchronize()
+        done = np.array([start.elapsed_time(e) / 1e3 for e in evs])
+        return done, done - arrivals
+
+    def server_run(arrivals):
+        srv = Server(budget_bytes=int(budget_gb * (1 << 30)), max_slots=slots)
+        try:
+            tickets = []
+            torch.cuda.synchronize()
+            t0 = time.monotonic_ns()
+            for q, a in zip(reqs, arrivals):
+                while time.monotonic_ns() - t0 < a * 1e9:
+                    pass
+                gb = None
+                if q["grads"] is not None:
+                    gb = dict(zip(("pos", "sigma", "values"), q["grads"]))
+                tickets.append(srv.submit(q["pos"], q["sig"], q["val"], q["r"].side, q["r"].side,
+                                          3.0, grad_out=q["G"], out=q["out"], grad_buffers=gb))
+            srv.drain()
+            res = [srv.result(t) for t in tickets]
+            assert all(x["state"] == _lib.DONE for x in res)
+            done = np.array([(x["t_done_ns"] - t0) / 1e9 for x in res])
+            return done, done - arrivals
+        finally:
+            srv.close()
+
+    def summary(done, lat):
+        mk = float(done.max())
+        return {"throughput_mpix_s": round(total_px / mk / 1e6, 1),
+                "requests_per_s": round(len(done) / mk, 1), "makespan_s": round(mk, 4),
+                "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3)}
+
+    zero = np.zeros(len(reqs))
+    launch_one(reqs[0])  # warm-up
+    torch.cuda.synchronize()
+    b_sat = summary(*baseline(zero))
+    log(f"serving baseline saturated: {b_sat}")
+    s_sat = summary(*server_run(zero))
+    log(f"serving server saturated:   {s_sat}")
+    rate = 0.8 * b_sat["requests_per_s"]
+    arr = np.array([r.arrival_s for r in synth.config4_trace(n_requests, rate, seed=seed)])
+    b_poi = summary(*baseline(arr))
+    log(f"serving baseline Poisson {rate:.0f}/s: {b_poi}")
+    s_poi = summary(*server_run(arr))
+    log(f"serving server   Poisson {rate:.0f}/s: {s_poi}")
+    return {"requests": n_requests, "poisson_rate_per_s": round(rate, 1),
+            "server": {"saturated": s_sat, "poisson": s_poi},
+            "one_launch_per_request": {"saturated": b_sat, "poisson": b_poi},
+            "saturated_speedup": round(s_sat["throughput_mpix_s"] / b_sat["throughput_mpix_s"], 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,6 +261,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="seconds of CPU work for the oracle baseline (0 disables)")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=4096)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -240,11 +357,7 @@ def main():
 
     serving = None
     if not args.no_serving:
-        try:
-            from paper_2012_13257_amd import serving_bench
-            serving = serving_bench.run(log)
-        except ImportError:
-            serving = None
+        serving = serving_benchmark(log, n_requests=args.serving_requests)
 
     res = {
         "metric": "output Mpix/s fwd+bwd at 1024x1024, N=1M (fwd-only and serving p50/p99 alongside)",

@@ -202,9 +202,11 @@ typedef struct interp_status {
  * resources, starts the scheduler thread). */
 int interp_server_create(const interp_server_config* cfg, interp_server** out);
 
-/* Non-blocking submit.  ENOMEM if the request can never fit the budget or the
- * slot table, EAGAIN if max_queue requests are pending, EINVAL for a bad
- * request.  On success *ticket identifies the request. */
+/* Non-blocking submit.  ENOMEM if the request can never fit the budget,
+ * EAGAIN if max_queue requests are pending, EINVAL for a bad request (B must
+ * be 1 and C at most 4 on the serving path).  The inputs must already be
+ * complete on the device: the server's streams do not wait for other
+ * streams.  On success *ticket identifies the request. */
 int interp_submit(interp_server* s, const interp_request* req, uint64_t* ticket);
 
 /* Non-blocking status query.  ENOTFOUND for an unknown ticket.  A ticket is

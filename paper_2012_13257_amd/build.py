@@ -49,8 +49,25 @@ def _compile(src: str) -> str:
     return obj
 
 
+SCHED_TEST_LIB = os.path.join(PKG, "libgmmsched_test.so")
+
+
+def build_sched_test() -> str:
+    """Host-only build of the scheduler test harness (fake executor, no HIP)."""
+    cxx = shutil.which("g++") or "g++"
+    tmp = SCHED_TEST_LIB + ".tmp"
+    cmd = [cxx, "-O2", "-std=c++17", "-fPIC", "-shared", "-pthread", "-Wall", "-I" + INCLUDE,
+           "-I" + CSRC, os.path.join(CSRC, "sched_selftest.cpp"), "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"g++ failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, SCHED_TEST_LIB)
+    return SCHED_TEST_LIB
+
+
 def build(verbose: bool = True) -> str:
-    """Compile every HIP source for gfx950 and link libgmminterp.so."""
+    """Compile every HIP source for gfx950 and link libgmminterp.so (and the
+    host-only scheduler test harness)."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
@@ -61,6 +78,7 @@ def build(verbose: bool = True) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    build_sched_test()
     if verbose:
         print(f"built {LIB}", file=sys.stderr)
     return LIB

@@ -124,49 +124,29 @@ __device__ inline void radix_hist(const ImageView& v, int p, int tile, int* lh) 
   __syncthreads();
 }
 
-// one 1024-thread block per image: exclusive scan of hist in digit-major order
-__device__ inline void radix_scan(const ImageView& v, int p, int* wsum, int* carry_s) {
+// unit = 4 digits (one wavefront per digit): exclusive scan of the digit's
+// per-tile counts over the tiles, in place, and the digit's total.
+__device__ inline void radix_scan_rows(const ImageView& v, int p, int unit) {
   int shift, width;
   radix_pass_bits(v, p, &shift, &width);
-  const int n = (1 << width) * v.ntiles;
-  int* h = v.hist;
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int lane = threadIdx.x & 63;
+  const int d = unit * 4 + (threadIdx.x >> 6);
+  if (d >= (1 << width)) return;
+  int* row = v.hist + (size_t)d * v.ntiles;
   int carry = 0;
-  for (int base = 0; base < n; base += 4096) {
-    int x[4];
-    const int i0 = base + tid * 4;
+  for (int base = 0; base < v.ntiles; base += 64) {
+    const int i = base + lane;
+    const int x = i < v.ntiles ? row[i] : 0;
+    int incl = x;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) x[q] = (i0 + q < n) ? h[i0 + q] : 0;
-    const int local = x[0] + x[1] + x[2] + x[3];
-    int incl = local;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const int t = __shfl_up(incl, d);
-      if (lane >= d) incl += t;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(incl, o);
+      if (lane >= o) incl += t;
     }
-    if (lane == 63) wsum[wid] = incl;
-    __syncthreads();
-    if (wid == 0) {
-      const int s = lane < 16 ? wsum[lane] : 0;
-      int si = s;
-#pragma unroll
-      for (int d = 1; d < 16; d <<= 1) {
-        const int t = __shfl_up(si, d);
-        if (lane >= d) si += t;
-      }
-      if (lane < 16) wsum[lane] = si - s;  // exclusive prefix of the wave sums
-      if (lane == 15) *carry_s = si;       // total of this stretch
-    }
-    __syncthreads();
-    int run = carry + wsum[wid] + incl - local;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (i0 + q < n) h[i0 + q] = run;
-      run += x[q];
-    }
-    carry += *carry_s;
-    __syncthreads();
+    if (i < v.ntiles) row[i] = carry + incl - x;
+    carry += __shfl(incl, 63);
   }
+  if (lane == 0) v.dtot[d] = carry;
 }
 
 // unit = one tile: stable scatter of (key, value) by the pass's digit.  Keys
@@ -184,8 +164,24 @@ __device__ inline void radix_scatter(const ImageView& v, int p, int tile, int* w
   int* kout = last ? v.keysF : ((p & 1) == 0 ? v.kA : v.kB);
   int* vout = last ? v.perm : ((p & 1) == 0 ? v.vA : v.vB);
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  // digit bases: exclusive scan of the digit totals (wave scans, then the
+  // four wave sums in order), plus this tile's offset within its digit
+  {
+    const int x = t < ndig ? v.dtot[t] : 0;
+    int incl = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(incl, o);
+      if (lane >= o) incl += y;
+    }
+    if (lane == 63) wcnt[wid] = incl;
+    __syncthreads();
+    int pre = 0;
+    for (int w = 0; w < wid; ++w) pre += wcnt[w];
+    base[t] = t < ndig ? pre + incl - x + v.hist[t * v.ntiles + tile] : 0;
+    __syncthreads();
+  }
   run[t] = 0;
-  base[t] = t < ndig ? v.hist[t * v.ntiles + tile] : 0;
   wcnt[t] = 0; wcnt[256 + t] = 0; wcnt[512 + t] = 0; wcnt[768 + t] = 0;
   __syncthreads();
   const unsigned long long below = (1ull << lane) - 1ull;

@@ -1,0 +1,344 @@
+// Serving loop: continuous batching of independent interpolation requests.
+//
+// Device side: a job table (one ImageView per admitted request plus, per
+// phase, the prefix sums of each job's work units) and one persistent
+// "job-table" kernel per phase.  Each kernel runs a fixed grid that strides
+// over the flattened work units of all jobs of the batch, finds the job of a
+// unit by binary search and calls the same device function as the
+// single-call path, so every request computes exactly the bits it would
+// compute alone.  The phase sequence (binning, forward, backward) is captured
+// once per batch context into a HIP graph; a batch is one table upload plus
+// one graph replay on the context's stream.  Per-job state lives in one
+// device arena allocated at creation (the HBM budget).
+//
+// Host side: the Scheduler (scheduler.hpp) admits requests by free slots and
+// arena space and launches batches on free contexts, so batches of requests
+// that arrive while others run execute concurrently on the device.
+#include <algorithm>
+#include <cstring>
+#include <string>
+
+#include "kernels.hpp"
+#include "scheduler.hpp"
+
+namespace gmm {
+
+int fail(int code, const std::string& msg);
+int fail_hip(hipError_t e, const char* where);
+
+namespace serve {
+
+constexpr int kMaxJobs = 256;      // jobs per batch (table capacity)
+constexpr int kContexts = 4;       // concurrent batches
+constexpr int kGrid = 1024;        // workgroups of every job-table kernel
+constexpr int kServeMaxC = 4;      // channels per request on the serving path
+constexpr int kServePasses = 3;    // radix passes the captured graph covers
+
+enum Phase {
+  PH_KEYS = 0,
+  PH_HIST0, PH_HIST1, PH_HIST2,
+  PH_SCAN0, PH_SCAN1, PH_SCAN2,
+  PH_SCAT0, PH_SCAT1, PH_SCAT2,
+  PH_FINISH, PH_GATHER, PH_FWD, PH_BPIX, PH_BPOINT, PH_BSIG,
+  PH_COUNT
+};
+
+struct JobTable {
+  int njobs;
+  int pad[3];
+  int units[PH_COUNT][kMaxJobs + 1];  // per phase: prefix sums of work units
+  int ct[kMaxJobs];                   // channel template of each job
+  ImageView view[kMaxJobs];           // last: only njobs entries are uploaded
+};
+
+// ---------------------------------------------------------------------------
+// Job-table kernels
+// ---------------------------------------------------------------------------
+
+template <int PH>
+__global__ __launch_bounds__(256) void kj_phase(const JobTable* __restrict__ T) {
+  __shared__ float red4[4];
+  __shared__ int lds_i[6 * 256];   // radix: wcnt[4*256], run[256], base[256]; hist: [256]
+  __shared__ float4 s_geo[4 * 64];
+  __shared__ float4 s_col[4 * 64];
+  const int nj = T->njobs;
+  const int* U = T->units[PH];
+  const int total = U[nj];
+  for (int u = blockIdx.x; u < total; u += gridDim.x) {
+    int lo = 0, hi = nj - 1;  // last job whose first unit is <= u
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (U[mid] <= u) lo = mid; else hi = mid - 1;
+    }
+    const int local = u - U[lo];
+    const ImageView& v = T->view[lo];
+    if constexpr (PH == PH_KEYS) {
+      dev::bin_keys(v, local, red4);
+    } else if constexpr (PH >= PH_HIST0 && PH <= PH_HIST2) {
+      dev::radix_hist(v, PH - PH_HIST0, local, lds_i);
+    } else if constexpr (PH >= PH_SCAN0 && PH <= PH_SCAN2) {
+      dev::radix_scan_rows(v, PH - PH_SCAN0, local);
+    } else if constexpr (PH >= PH_SCAT0 && PH <= PH_SCAT2) {
+      dev::radix_scatter(v, PH - PH_SCAT0, local, lds_i, lds_i + 1024, lds_i + 1280);
+    } else if constexpr (PH == PH_FINISH) {
+      dev::bin_finish(v, local, red4);
+    } else if constexpr (PH == PH_GATHER) {
+      dev::bin_gather(v, local);
+    } else if constexpr (PH == PH_FWD) {
+      switch (T->ct[lo]) {
+        case 1: dev::forward_tile<1>(v, local, s_geo, s_col); break;
+        case 2: dev::forward_tile<2>(v, local, s_geo, s_col); break;
+        case 3: dev::forward_tile<3>(v, local, s_geo, s_col); break;
+        default: dev::forward_tile<4>(v, local, s_geo, s_col); break;
+      }
+    } else if constexpr (PH == PH_BPIX) {
+      switch (T->ct[lo]) {
+        case 1: dev::bwd_pixel<1>(v, local); break;
+        case 2: dev::bwd_pixel<2>(v, local); break;
+        case 3: dev::bwd_pixel<3>(v, local); break;
+        default: dev::bwd_pixel<4>(v, local); break;
+      }
+    } else if constexpr (PH == PH_BPOINT) {
+      switch (T->ct[lo]) {
+        case 1: dev::bwd_point<1>(v, local, red4); break;
+        case 2: dev::bwd_point<2>(v, local, red4); break;
+        case 3: dev::bwd_point<3>(v, local, red4); break;
+        default: dev::bwd_point<4>(v, local, red4); break;
+      }
+    } else if constexpr (PH == PH_BSIG) {
+      dev::bwd_sigma_sum(v, red4);
+    }
+    __syncthreads();
+  }
+}
+
+template <int PH>
+void enqueue_phase(const JobTable* dtab, hipStream_t st) {
+  hipLaunchKernelGGL(kj_phase<PH>, dim3(kGrid), dim3(256), 0, st, dtab);
+}
+
+// ---------------------------------------------------------------------------
+// GPU executor
+// ---------------------------------------------------------------------------
+
+struct Request {
+  interp_request r;
+  Geometry g;
+  Layout L;
+};
+
+class GpuExecutor {
+ public:
+  int contexts() const { return kContexts; }
+  int max_batch() const { return kMaxJobs; }
+
+  int init(int device, uint64_t budget) {
+    device_ = device;
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) return fail_hip(e, "hipSetDevice");
+    if (budget) {
+      e = hipMalloc(&arena_, budget);
+      if (e != hipSuccess) return fail_hip(e, "hipMalloc(arena)");
+    }
+    for (int c = 0; c < kContexts; ++c) {
+      Ctx& x = ctx_[c];
+      if ((e = hipMalloc(&x.dtab, sizeof(JobTable))) != hipSuccess) return fail_hip(e, "hipMalloc(table)");
+      if ((e = hipHostMalloc(&x.htab, sizeof(JobTable))) != hipSuccess) return fail_hip(e, "hipHostMalloc(table)");
+      std::memset(x.htab, 0, sizeof(JobTable));
+      if ((e = hipStreamCreateWithFlags(&x.stream, hipStreamNonBlocking)) != hipSuccess)
+        return fail_hip(e, "hipStreamCreate");
+      if ((e = hipEventCreateWithFlags(&x.done, hipEventDisableTiming)) != hipSuccess)
+        return fail_hip(e, "hipEventCreate");
+      // an empty table so that the capture below reads defined memory
+      if ((e = hipMemcpy(x.dtab, x.htab, sizeof(JobTable), hipMemcpyHostToDevice)) != hipSuccess)
+        return fail_hip(e, "hipMemcpy(table)");
+      // capture the phase sequence once; every batch replays it
+      if ((e = hipStreamBeginCapture(x.stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+        return fail_hip(e, "hipStreamBeginCapture");
+      enqueue_phase<PH_KEYS>(x.dtab, x.stream);
+      enqueue_phase<PH_HIST0>(x.dtab, x.stream);
+      enqueue_phase<PH_SCAN0>(x.dtab, x.stream);
+      enqueue_phase<PH_SCAT0>(x.dtab, x.stream);
+      enqueue_phase<PH_HIST1>(x.dtab, x.stream);
+      enqueue_phase<PH_SCAN1>(x.dtab, x.stream);
+      enqueue_phase<PH_SCAT1>(x.dtab, x.stream);
+      enqueue_phase<PH_HIST2>(x.dtab, x.stream);
+      enqueue_phase<PH_SCAN2>(x.dtab, x.stream);
+      enqueue_phase<PH_SCAT2>(x.dtab, x.stream);
+      enqueue_phase<PH_FINISH>(x.dtab, x.stream);
+      enqueue_phase<PH_GATHER>(x.dtab, x.stream);
+      enqueue_phase<PH_FWD>(x.dtab, x.stream);
+      enqueue_phase<PH_BPIX>(x.dtab, x.stream);
+      enqueue_phase<PH_BPOINT>(x.dtab, x.stream);
+      enqueue_phase<PH_BSIG>(x.dtab, x.stream);
+      hipGraph_t graph = nullptr;
+      e = hipStreamEndCapture(x.stream, &graph);
+      if (e != hipSuccess) return fail_hip(e, "hipStreamEndCapture");
+      e = hipGraphInstantiate(&x.exec, graph, nullptr, nullptr, 0);
+      hipGraphDestroy(graph);
+      if (e != hipSuccess) return fail_hip(e, "hipGraphInstantiate");
+    }
+    return INTERP_OK;
+  }
+
+  void release() {
+    hipSetDevice(device_);
+    for (int c = 0; c < kContexts; ++c) {
+      Ctx& x = ctx_[c];
+      if (x.stream) hipStreamSynchronize(x.stream);
+      if (x.exec) hipGraphExecDestroy(x.exec);
+      if (x.done) hipEventDestroy(x.done);
+      if (x.stream) hipStreamDestroy(x.stream);
+      if (x.htab) hipHostFree(x.htab);
+      if (x.dtab) hipFree(x.dtab);
+      x = Ctx{};
+    }
+    if (arena_) hipFree(arena_);
+    arena_ = nullptr;
+  }
+
+  void thread_init() { hipSetDevice(device_); }
+
+  int launch(int c, std::vector<Job<Request>*>& jobs) {
+    Ctx& x = ctx_[c];
+    JobTable* T = x.htab;
+    const int nj = (int)jobs.size();
+    T->njobs = nj;
+    for (int ph = 0; ph < PH_COUNT; ++ph) T->units[ph][0] = 0;
+    for (int i = 0; i < nj; ++i) {
+      const Request& rq = jobs[i]->req;
+      const Geometry& g = rq.g;
+      char* base = static_cast<char*>(arena_) + jobs[i]->arena_off;
+      const interp_request& r = rq.r;
+      T->view[i] = make_view(g, rq.L, base, base + rq.L.saved_bytes, r.pos, r.sigma, r.values, r.out,
+                             r.grad_out, r.grad_out ? r.grad_pos : nullptr,
+                             r.grad_out ? r.grad_sigma : nullptr,
+                             r.grad_out ? r.grad_values : nullptr);
+      T->ct[i] = g.CT;
+      const bool bwd = r.grad_out != nullptr;
+      int u[PH_COUNT] = {};
+      u[PH_KEYS] = g.N > 0 ? g.units256 : 0;
+      for (int p = 0; p < kServePasses; ++p) {
+        const bool on = p < g.npass && g.N > 0;
+        const int width = on ? std::min(g.dbits, g.kbits - p * g.dbits) : 0;
+        u[PH_HIST0 + p] = on ? g.ntiles : 0;
+        u[PH_SCAN0 + p] = on ? ((1 << width) + 3) / 4 : 0;
+        u[PH_SCAT0 + p] = on ? g.ntiles : 0;
+      }
+      u[PH_FINISH] = dev::finish_units(g.N);
+      u[PH_GATHER] = g.N > 0 ? g.units256 : 0;
+      u[PH_FWD] = dev::fwd_tiles(g.bx_blocks, g.by_blocks);
+      u[PH_BPIX] = bwd ? (g.H * g.W + 255) / 256 : 0;
+      u[PH_BPOINT] = bwd && g.N > 0 ? g.units256 : 0;
+      u[PH_BSIG] = bwd && !g.per_point && r.grad_sigma ? 1 : 0;
+      for (int ph = 0; ph < PH_COUNT; ++ph) T->units[ph][i + 1] = T->units[ph][i] + u[ph];
+    }
+    const size_t bytes = offsetof(JobTable, view) + sizeof(ImageView) * (size_t)nj;
+    hipError_t e = hipMemcpyAsync(x.dtab, T, bytes, hipMemcpyHostToDevice, x.stream);
+    if (e != hipSuccess) return fail_hip(e, "hipMemcpyAsync(table)");
+    e = hipGraphLaunch(x.exec, x.stream);
+    if (e != hipSuccess) return fail_hip(e, "hipGraphLaunch");
+    e = hipEventRecord(x.done, x.stream);
+    if (e != hipSuccess) return fail_hip(e, "hipEventRecord");
+    return INTERP_OK;
+  }
+
+  int query(int c) {
+    const hipError_t e = hipEventQuery(ctx_[c].done);
+    if (e == hipSuccess) return 1;
+    if (e == hipErrorNotReady) return 0;
+    fail_hip(e, "batch");
+    return INTERP_EHIP;
+  }
+
+  void wait(int c) { hipEventSynchronize(ctx_[c].done); }
+
+ private:
+  struct Ctx {
+    JobTable* dtab = nullptr;
+    JobTable* htab = nullptr;
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    hipGraphExec_t exec = nullptr;
+  };
+  int device_ = 0;
+  void* arena_ = nullptr;
+  Ctx ctx_[kContexts];
+};
+
+}  // namespace serve
+}  // namespace gmm
+
+struct interp_server {
+  gmm::serve::GpuExecutor exec;
+  std::unique_ptr<gmm::serve::Scheduler<gmm::serve::Request, gmm::serve::GpuExecutor>> sched;
+};
+
+using namespace gmm;
+
+extern "C" {
+
+int interp_server_create(const interp_server_config* cfg, interp_server** out) {
+  if (!cfg || !out) return fail(INTERP_EINVAL, "NULL argument");
+  if (cfg->max_slots < 1 || cfg->max_slots > 1024) return fail(INTERP_EINVAL, "max_slots must be in [1, 1024]");
+  if (cfg->max_queue < 1) return fail(INTERP_EINVAL, "max_queue must be >= 1");
+  if (cfg->hbm_budget_bytes == 0) return fail(INTERP_EINVAL, "hbm_budget_bytes must be > 0");
+  auto* s = new interp_server();
+  int rc = s->exec.init(cfg->device, cfg->hbm_budget_bytes);
+  if (rc != INTERP_OK) {
+    s->exec.release();
+    delete s;
+    return rc;
+  }
+  s->sched.reset(new serve::Scheduler<serve::Request, serve::GpuExecutor>(
+      &s->exec, cfg->hbm_budget_bytes, cfg->max_slots, cfg->max_queue));
+  *out = s;
+  return INTERP_OK;
+}
+
+int interp_submit(interp_server* s, const interp_request* req, uint64_t* ticket) {
+  if (!s || !req || !ticket) return fail(INTERP_EINVAL, "NULL argument");
+  serve::Request rq;
+  rq.r = *req;
+  std::string m = make_geometry(&req->prob, &rq.g);
+  if (!m.empty()) return fail(INTERP_EINVAL, m);
+  if (rq.g.B != 1) return fail(INTERP_EINVAL, "a serving request has B = 1");
+  if (rq.g.C > serve::kServeMaxC) return fail(INTERP_EINVAL, "the serving path takes C <= 4");
+  if (rq.g.npass > serve::kServePasses) return fail(INTERP_EINVAL, "too many bins for the serving path");
+  if (rq.g.N > 0 && (!req->pos || !req->sigma || !req->values))
+    return fail(INTERP_EINVAL, "pos, sigma and values must not be NULL when N > 0");
+  if (!req->sigma && !rq.g.per_point && rq.g.N > 0) return fail(INTERP_EINVAL, "sigma must not be NULL");
+  if (!req->out) return fail(INTERP_EINVAL, "out must not be NULL");
+  if ((req->pos && (uintptr_t)req->pos % 8) || (req->grad_pos && (uintptr_t)req->grad_pos % 8))
+    return fail(INTERP_EINVAL, "pos and grad_pos must be 8-byte aligned");
+  rq.L = make_layout(rq.g);
+  const uint64_t bytes = serve::Arena::round(rq.L.saved_bytes) + serve::Arena::round(rq.L.work_bytes);
+  rq.L.saved_bytes = serve::Arena::round(rq.L.saved_bytes);  // workspace starts at the next grain
+  const int rc = s->sched->submit(rq, bytes, ticket);
+  if (rc == INTERP_ENOMEM) return fail(rc, "request can never fit the server's memory budget");
+  if (rc == INTERP_EAGAIN) return fail(rc, "server queue is full");
+  return rc;
+}
+
+int interp_poll(interp_server* s, uint64_t ticket, interp_status* status) {
+  if (!s || !status) return fail(INTERP_EINVAL, "NULL argument");
+  const int rc = s->sched->poll(ticket, status);
+  if (rc == INTERP_ENOTFOUND) return fail(rc, "unknown ticket");
+  return rc;
+}
+
+int interp_server_drain(interp_server* s, int64_t timeout_ms) {
+  if (!s) return fail(INTERP_EINVAL, "NULL argument");
+  return s->sched->drain(timeout_ms);
+}
+
+int interp_server_destroy(interp_server* s) {
+  if (!s) return fail(INTERP_EINVAL, "NULL argument");
+  s->sched->shutdown();
+  s->sched.reset();
+  s->exec.release();
+  delete s;
+  return INTERP_OK;
+}
+
+}  // extern "C"

@@ -1,5 +1,7 @@
 // Single-call path: one launch per phase over every image of one problem
 // (grid.y = image, or a flattened XCD-aware grid for the forward gather).
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace gmm {
@@ -15,10 +17,8 @@ __global__ __launch_bounds__(256) void k_radix_hist(ImageView v0, int p) {
   dev::radix_hist(image_of(v0, blockIdx.y), p, blockIdx.x, lh);
 }
 
-__global__ __launch_bounds__(1024) void k_radix_scan(ImageView v0, int p) {
-  __shared__ int wsum[16];
-  __shared__ int carry;
-  dev::radix_scan(image_of(v0, blockIdx.x), p, wsum, &carry);
+__global__ __launch_bounds__(256) void k_radix_scan(ImageView v0, int p) {
+  dev::radix_scan_rows(image_of(v0, blockIdx.y), p, blockIdx.x);
 }
 
 __global__ __launch_bounds__(256) void k_radix_scatter(ImageView v0, int p) {
@@ -122,7 +122,8 @@ hipError_t launch_forward_all(const Geometry& g, const ImageView& v0, hipStream_
     }
     {
       ProfRange pr_("radix_scan", st);
-      hipLaunchKernelGGL(k_radix_scan, dim3(g.B), dim3(1024), 0, st, v0, p);
+      const int width = std::min(g.dbits, g.kbits - p * g.dbits);
+      hipLaunchKernelGGL(k_radix_scan, dim3(cdiv(1 << width, 4), g.B), dim3(256), 0, st, v0, p);
     }
     {
       ProfRange pr_("radix_scatter", st);

@@ -1,0 +1,115 @@
+"""Python binding of the serving loop (interp_server_* in libgmminterp.so).
+
+    srv = Server(budget_bytes=8 << 30, max_slots=128)
+    t = srv.submit(pos, sigma, values, H, W)            # forward only
+    t = srv.submit(pos, sigma, values, H, W, grad_out=G) # forward + backward
+    ...
+    res = srv.result(t)   # None while queued/running; dict when done
+
+Every request is one image (B = 1) with C <= 4 channels.  Inputs must be
+complete on the device before submit (the server's streams do not wait for
+other streams); outputs are allocated here and returned once the request is
+done.  The binding keeps every tensor of a request alive until its result
+has been collected.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Dict, Optional
+
+import torch
+
+from . import _lib
+from .interp import problem
+
+
+class Server:
+    def __init__(self, budget_bytes: int, max_slots: int = 128, max_queue: int = 1 << 20,
+                 device: Optional[int] = None):
+        L = _lib.lib()
+        dev = torch.cuda.current_device() if device is None else int(device)
+        cfg = _lib.ServerConfig(dev, int(max_slots), int(max_queue), 0, int(budget_bytes))
+        h = ctypes.c_void_p()
+        _lib.check("interp_server_create", L.interp_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._device = torch.device("cuda", dev)
+        self._live: Dict[int, dict] = {}
+
+    def submit(self, pos, sigma, values, H: int, W: int, radius: float = 3.0, tile: int = 8,
+               grad_out: Optional[torch.Tensor] = None, grads=("pos", "sigma", "values"),
+               out: Optional[torch.Tensor] = None, grad_buffers: Optional[dict] = None) -> int:
+        """Queues one request.  out / grad_buffers ({"pos": t, "sigma": t,
+        "values": t}) may supply preallocated result tensors."""
+        prob = problem(pos, sigma, values, H, W, radius, tile)
+        if out is None:
+            out = torch.empty((1, prob.C, prob.H, prob.W), dtype=torch.float32, device=self._device)
+        elif tuple(out.shape) != (1, prob.C, prob.H, prob.W) or not out.is_contiguous():
+            raise ValueError("out must be a contiguous [1, C, H, W] tensor")
+        gb = grad_buffers or {}
+        keep = {"pos": pos, "sigma": sigma, "values": values, "out": out}
+        req = _lib.Request()
+        req.prob = prob
+        req.pos, req.sigma, req.values, req.out = (pos.data_ptr(), sigma.data_ptr(),
+                                                   values.data_ptr(), out.data_ptr())
+        if grad_out is not None:
+            if tuple(grad_out.shape) != (1, prob.C, prob.H, prob.W) or not grad_out.is_contiguous():
+                raise ValueError("grad_out must be a contiguous [1, C, H, W] tensor")
+            keep["grad_out"] = grad_out
+            req.grad_out = grad_out.data_ptr()
+            if "pos" in grads:
+                keep["grad_pos"] = gb["pos"] if "pos" in gb else torch.empty_like(pos)
+                req.grad_pos = keep["grad_pos"].data_ptr()
+            if "sigma" in grads:
+                keep["grad_sigma"] = gb["sigma"] if "sigma" in gb else torch.empty_like(sigma)
+                req.grad_sigma = keep["grad_sigma"].data_ptr()
+            if "values" in grads:
+                keep["grad_values"] = gb["values"] if "values" in gb else torch.empty_like(values)
+                req.grad_values = keep["grad_values"].data_ptr()
+        ticket = ctypes.c_uint64()
+        _lib.check("interp_submit", _lib.lib().interp_submit(self._h, ctypes.byref(req),
+                                                             ctypes.byref(ticket)))
+        self._live[ticket.value] = keep
+        return ticket.value
+
+    def poll(self, ticket: int) -> _lib.Status:
+        st = _lib.Status()
+        _lib.check("interp_poll", _lib.lib().interp_poll(self._h, ticket, ctypes.byref(st)))
+        return st
+
+    def result(self, ticket: int):
+        """None while the request is queued or running; otherwise a dict with the
+        status fields and the output tensors (out, grad_*) of the request."""
+        st = self.poll(ticket)
+        if st.state in (_lib.QUEUED, _lib.RUNNING):
+            return None
+        keep = self._live.pop(ticket)
+        res = {k: v for k, v in keep.items() if k == "out" or k.startswith("grad_")}
+        res.pop("grad_out", None)
+        res.update(state=st.state, err=st.err, t_submit_ns=st.t_submit_ns,
+                   t_admit_ns=st.t_admit_ns, t_done_ns=st.t_done_ns)
+        return res
+
+    def drain(self, timeout_ms: int = -1) -> bool:
+        rc = _lib.lib().interp_server_drain(self._h, int(timeout_ms))
+        if rc == _lib.INTERP_EAGAIN:
+            return False
+        _lib.check("interp_server_drain", rc)
+        return True
+
+    def close(self) -> None:
+        if self._h:
+            _lib.check("interp_server_destroy", _lib.lib().interp_server_destroy(self._h))
+            self._h = None
+            self._live.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
