@@ -29,7 +29,18 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 CU, SIMD_LANES_PER_CU, CLOCK_GHZ = 256, 64, 2.4
 VALU_PEAK_TLANEOPS = CU * SIMD_LANES_PER_CU * CLOCK_GHZ / 1000.0   # 39.32 T lane-ops/s
-EXP_SLOTS = 4  # v_exp_f32 is a quarter-rate transcendental: 4 issue slots per lane
+# Algorithmic VALU lane-ops per pixel-point pair inside the radius (the exp
+# counts as one: measured, it overlaps fully with the other VALU work):
+#   forward  2 sub + 2 mul + 1 add (d2), 1 mul (exponent), 1 exp, 1 cmp,
+#            1 select, 1 add (Z), C FMAs                       = 10 + C
+#   backward 1 sub + 1 mul + 1 add (d2, the row term amortised), 1 cmp,
+#            1 mul, 1 exp, C FMAs (A), C FMAs (dL/dc), 1 mul, 3 FMAs = 11 + 2C
+def fwd_ops(C):
+    return 10 + C
+
+
+def bwd_ops(C):
+    return 11 + 2 * C
 
 
 def pair_count(pos: np.ndarray, sigma: np.ndarray, H: int, W: int, radius: float) -> int:
@@ -135,6 +146,55 @@ def cpu_baseline(wl, G, budget_s: float):
                       f"{wl.H}x{wl.W} N={wl.N} workload, extrapolated linearly to the full image "
                       f"(fwd {t_fwd * 1e3:.2f} ms/pixel, bwd {t_bwd * 1e3:.1f} ms/point)",
             "fwd_mpix_s": 1.0 / t_fwd / 1e6}
+
+
+def measure_peaks(log):
+    """Measured ceilings: VALU FMA rate, v_exp_f32 rate, a 1 exp : 6 VALU mix,
+    and an HBM copy (also the reference kernel of known size for the byte
+    counters)."""
+    import ctypes
+    import torch
+    from paper_2012_13257_amd.build import PEAK_LIB
+    lib = ctypes.CDLL(PEAK_LIB)
+    lib.gmm_peak_launch.restype = ctypes.c_double
+    lib.gmm_peak_launch.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_longlong, ctypes.c_void_p]
+    st = torch.cuda.current_stream().cuda_stream
+    out = torch.zeros(1 << 16, device="cuda")
+    n4 = (512 << 20) // 16
+    src = torch.ones(n4 * 4, device="cuda")
+    dst = torch.empty_like(src)
+    res = {}
+    for which, name in ((0, "fma"), (1, "exp"), (2, "mix"), (3, "copy")):
+        def go():
+            v = lib.gmm_peak_launch(which, 0, out.data_ptr(), src.data_ptr(), dst.data_ptr(), n4, st)
+            if v < 0:
+                raise RuntimeError("peak kernel launch failed")
+            return v
+        go()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        reps = 5
+        for _ in range(reps):
+            work = go()
+        b.record()
+        torch.cuda.synchronize()
+        sec = a.elapsed_time(b) / 1e3 / reps
+        res[name] = work / sec
+    peaks = {"valu_fma_tlaneops": round(res["fma"] / 1e12, 2),
+             "exp_tlaneops": round(res["exp"] / 1e12, 2),
+             "mix_iter_per_ns_per_lane": None,
+             "exp_issue_slots": round(res["fma"] / res["exp"], 2),
+             "hbm_copy_gbs": round(res["copy"] / 1e9, 1)}
+    # mix: 7 VALU instructions per chain-iteration, one of them exp
+    mix_inst = res["mix"] * 7
+    peaks["mix_tlaneops"] = round(mix_inst / 1e12, 2)
+    peaks.pop("mix_iter_per_ns_per_lane")
+    log(f"measured ceilings: {peaks}")
+    del src, dst
+    return peaks
 
 
 def serving_benchmark(log, n_requests: int = 4096, seed: int = 1004, budget_gb: float = 24.0,
@@ -276,6 +336,7 @@ def main():
         sys.exit(1)
     log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)  # noqa: E731
 
+    peaks = measure_peaks(log)
     wl = synth.config3()
     G_np = wl.grad_out()
     log("workload", wl.name, "B", wl.B, "N", wl.N, "C", wl.C, "HxW", wl.H, wl.W)
@@ -323,8 +384,8 @@ def main():
     P = pair_count(wl.pos, wl.sigma, wl.H, wl.W, wl.radius)
     log(f"pairs inside the radius P = {P} ({time.perf_counter() - t0:.1f} s to count)")
     C = wl.C
-    ops_fwd_pair = 8 + C + EXP_SLOTS          # d2 (5), k*d2, cmp/select, Z add, C FMAs; exp
-    ops_bwd_pair = 13 + 2 * C + EXP_SLOTS     # d2 (3 with the row term), exp arg, A (C), gc (C), 4 for x/y/s
+    ops_fwd_pair = fwd_ops(C)
+    ops_bwd_pair = bwd_ops(C)
     dom = max(kernels.items(), key=lambda kv: kv[1]["avg_us"])
     name, info = dom
     if name == "forward":
@@ -340,7 +401,7 @@ def main():
                 "peak": round(VALU_PEAK_TLANEOPS, 2), "unit": "Tlaneop/s",
                 "frac": round(achieved / VALU_PEAK_TLANEOPS, 4), "traffic": None,
                 "work_per_launch": f"P={P} pairs x {ops_fwd_pair if name == 'forward' else ops_bwd_pair} "
-                                   "lane-op slots (exp = 4)",
+                                   "VALU lane-ops",
                 "kernel_avg_us": round(info["avg_us"], 2)}
     other = {}
     for kname, ops in (("forward", ops_fwd_pair), ("bwd_point", ops_bwd_pair)):
@@ -380,6 +441,7 @@ def main():
         "kernels_us": {k: round(v["avg_us"], 2) for k, v in kernels.items()},
         "kernel_alu": other,
         "roofline": roof,
+        "measured_ceilings": peaks,
         "cpu_baseline": cpu,
         "serving": serving,
     }

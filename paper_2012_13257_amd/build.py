@@ -50,6 +50,19 @@ def _compile(src: str) -> str:
 
 
 SCHED_TEST_LIB = os.path.join(PKG, "libgmmsched_test.so")
+PEAK_LIB = os.path.join(PKG, "libgmmpeak.so")
+
+
+def build_peak() -> str:
+    """Ceiling microbenchmarks (measurement tooling used by bench.py)."""
+    obj = _compile("peak.hip")
+    tmp = PEAK_LIB + ".tmp"
+    cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, PEAK_LIB)
+    return PEAK_LIB
 
 
 def build_sched_test() -> str:
@@ -79,6 +92,7 @@ def build(verbose: bool = True) -> str:
         raise RuntimeError(f"link failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
     build_sched_test()
+    build_peak()
     if verbose:
         print(f"built {LIB}", file=sys.stderr)
     return LIB

@@ -270,16 +270,27 @@ __host__ __device__ inline int fwd_tiles(int bx_blocks, int by_blocks) {
   return ((bx_blocks + 1) / 2) * ((by_blocks + 1) / 2);
 }
 
+// float4 elements of LDS a 256-thread forward block needs: per wavefront,
+// 64 candidate records + one sentinel, their values, and four 64-entry lists.
+__host__ __device__ constexpr int fwd_lds_per_wave(int CS) { return 65 + 65 * (CS / 4) + 64; }
+__host__ __device__ constexpr int fwd_lds_float4(int CS) { return 4 * fwd_lds_per_wave(CS); }
+
 // One 256-thread block = one 16x16 pixel tile; wavefront w owns the 8x8
-// block (w & 1, w >> 1) of it, one pixel per lane.  Candidates are the
+// block (w & 1, w >> 1) of it, and its four 16-lane quarters own the four
+// 4x4 quadrants of that block (one pixel per lane).  Candidates are the
 // records of the bins within reach of the block (one contiguous range per
 // bin row), taken 64 at a time: each lane tests one candidate's disk against
-// the block, the hits are compacted in candidate order into the wavefront's
-// LDS list, and every lane then evaluates each hit for its pixel.
+// the four quadrants; candidates reaching any quadrant are staged in LDS and
+// every quadrant gets the list of its own hits, in candidate order (shorter
+// lists are padded with a sentinel record that never passes the radius
+// test).  The quarters then walk their lists in lockstep, every lane
+// evaluating the radius test and the weight for its pixel.  A pixel sums the
+// same nonzero terms in the same (sorted) order as any other split of the
+// work, so the result does not depend on the block shape.
 template <int CT>
-__device__ inline void forward_tile(const ImageView& v, int tile, float4* s_geo /*[4][64]*/,
-                                    float4* s_col /*[4][64*CS/4]*/) {
+__device__ inline void forward_tile(const ImageView& v, int tile, float4* lds) {
   constexpr int CS = CT < 4 ? 4 : CT;
+  constexpr int Q = CS / 4;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int wgx = fwd_tiles_x(v.bx_blocks);
   const int ty = tile / wgx, tx = tile - ty * wgx;
@@ -288,8 +299,26 @@ __device__ inline void forward_tile(const ImageView& v, int tile, float4* s_geo 
   if (u0 >= v.W || v0 >= v.H) return;
   const int ue = min(u0 + kBlockSide - 1, v.W - 1);
   const int ve = min(v0 + kBlockSide - 1, v.H - 1);
-  const int u = u0 + (lane & 7), vv = v0 + (lane >> 3);
+  const int q = lane >> 4, pq = lane & 15;
+  const int u = u0 + (q & 1) * 4 + (pq & 3);
+  const int vv = v0 + (q >> 1) * 4 + (pq >> 2);
   const float fu = (float)u, fv = (float)vv;
+  // quadrant bounds, clipped to the image (an empty right / bottom pair is
+  // marked by a lower bound above the upper one)
+  const float xl0 = (float)u0, xl1 = (float)min(u0 + 3, ue);
+  const float xr0 = (float)(u0 + 4), xr1 = (float)min(u0 + 7, ue);
+  const float yt0 = (float)v0, yt1 = (float)min(v0 + 3, ve);
+  const float yb0 = (float)(v0 + 4), yb1 = (float)min(v0 + 7, ve);
+  const bool has_r = u0 + 4 <= ue, has_b = v0 + 4 <= ve;
+
+  float4* cgeo = lds + wid * fwd_lds_per_wave(CS);
+  float4* ccol = cgeo + 65;
+  int* lists = reinterpret_cast<int*>(ccol + 65 * Q);  // [4][64]
+  if (lane == 0) {
+    cgeo[64] = make_float4(0.0f, 0.0f, 0.0f, -1.0f);  // sentinel: R2 < 0 never passes
+#pragma unroll
+    for (int k = 0; k < Q; ++k) ccol[64 * Q + k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  }
 
   // float math runs on the vector ALU; readfirstlane keeps the wave-uniform
   // loop bounds in scalar registers
@@ -299,48 +328,66 @@ __device__ inline void forward_tile(const ImageView& v, int tile, float4* s_geo 
   const int by_lo = __builtin_amdgcn_readfirstlane(bin_coord((float)v0 - Rh, v.inv_tile, v.nby));
   const int by_hi = __builtin_amdgcn_readfirstlane(bin_coord((float)ve + Rh, v.inv_tile, v.nby));
   const float4* gb = v.geo;
-  const float* cb = v.col;
+  const float4* cb = reinterpret_cast<const float4*>(v.col);
 
   float Z = 0.0f;
   float acc[CT];
 #pragma unroll
   for (int k = 0; k < CT; ++k) acc[k] = 0.0f;
-
-  float4* lgeo = s_geo + wid * 64;
-  float4* lcol = s_col + wid * 64 * (CS / 4);
+  const int* mylist = lists + q * 64;
 
   for (int by = by_lo; by <= by_hi; ++by) {
     const int s = __builtin_amdgcn_readfirstlane(v.offset[by * v.nbx + bx_lo]);
     const int e = __builtin_amdgcn_readfirstlane(v.offset[by * v.nbx + bx_hi + 1]);
     for (int c0 = s; c0 < e; c0 += 64) {
       const int jc = c0 + lane;
-      bool hit = false;
+      bool h0 = false, h1 = false, h2 = false, h3 = false;
       float4 g = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       if (jc < e) {
         g = gb[jc];
-        const float ex = fmaxf(fmaxf((float)u0 - g.x, g.x - (float)ue), 0.0f);
-        const float ey = fmaxf(fmaxf((float)v0 - g.y, g.y - (float)ve), 0.0f);
-        hit = ex * ex + ey * ey <= g.w * 1.001f + 1e-6f;
+        // distance from the disk centre to each quadrant (conservative test)
+        const float exl = fmaxf(fmaxf(xl0 - g.x, g.x - xl1), 0.0f);
+        const float exr = has_r ? fmaxf(fmaxf(xr0 - g.x, g.x - xr1), 0.0f) : 1e30f;
+        const float eyt = fmaxf(fmaxf(yt0 - g.y, g.y - yt1), 0.0f);
+        const float eyb = has_b ? fmaxf(fmaxf(yb0 - g.y, g.y - yb1), 0.0f) : 1e30f;
+        const float lim = g.w * 1.001f + 1e-6f;
+        h0 = exl * exl + eyt * eyt <= lim;
+        h1 = exr * exr + eyt * eyt <= lim;
+        h2 = exl * exl + eyb * eyb <= lim;
+        h3 = exr * exr + eyb * eyb <= lim;
       }
-      const unsigned long long mask = __ballot(hit);
-      if (mask == 0) continue;
-      if (hit) {
-        const int slot = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
-                                                   __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0));
-        lgeo[slot] = g;
-        const float4* cp = reinterpret_cast<const float4*>(cb + (size_t)jc * CS);
+      const bool any = h0 || h1 || h2 || h3;
+      const unsigned long long many = __ballot(any);
+      if (many == 0) continue;
+      const int slot = __builtin_amdgcn_mbcnt_hi((unsigned)(many >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((unsigned)many, 0));
+      if (any) {
+        cgeo[slot] = g;
 #pragma unroll
-        for (int q = 0; q < CS / 4; ++q) lcol[slot * (CS / 4) + q] = cp[q];
+        for (int k = 0; k < Q; ++k) ccol[slot * Q + k] = cb[(size_t)jc * Q + k];
       }
+      const unsigned long long m0 = __ballot(h0), m1 = __ballot(h1);
+      const unsigned long long m2 = __ballot(h2), m3 = __ballot(h3);
+      const int n0 = __popcll(m0), n1 = __popcll(m1), n2 = __popcll(m2), n3 = __popcll(m3);
+      const int nmax = max(max(n0, n1), max(n2, n3));
+#define GMM_LIST_PUT(qq, mq, hq, nq)                                                          \
+      if (hq) lists[qq * 64 + __builtin_amdgcn_mbcnt_hi((unsigned)(mq >> 32),                 \
+                    __builtin_amdgcn_mbcnt_lo((unsigned)mq, 0))] = slot;                       \
+      if (lane >= nq && lane < nmax) lists[qq * 64 + lane] = 64;
+      GMM_LIST_PUT(0, m0, h0, n0)
+      GMM_LIST_PUT(1, m1, h1, n1)
+      GMM_LIST_PUT(2, m2, h2, n2)
+      GMM_LIST_PUT(3, m3, h3, n3)
+#undef GMM_LIST_PUT
       wave_lds_sync();
-      const int nh = __popcll(mask);
-      for (int i = 0; i < nh; ++i) {
-        const float4 r = lgeo[i];
+      for (int i = 0; i < nmax; ++i) {
+        const int idx = mylist[i];
+        const float4 r = cgeo[idx];
         float cc[CS];
 #pragma unroll
-        for (int q = 0; q < CS / 4; ++q) {
-          const float4 tq = lcol[i * (CS / 4) + q];
-          cc[4 * q] = tq.x; cc[4 * q + 1] = tq.y; cc[4 * q + 2] = tq.z; cc[4 * q + 3] = tq.w;
+        for (int k = 0; k < Q; ++k) {
+          const float4 tq = ccol[idx * Q + k];
+          cc[4 * k] = tq.x; cc[4 * k + 1] = tq.y; cc[4 * k + 2] = tq.z; cc[4 * k + 3] = tq.w;
         }
         // radius test exactly as specified: float32, every operation rounded
         const float dx = fu - r.x;

@@ -59,8 +59,7 @@ template <int PH>
 __global__ __launch_bounds__(256) void kj_phase(const JobTable* __restrict__ T) {
   __shared__ float red4[4];
   __shared__ int lds_i[6 * 256];   // radix: wcnt[4*256], run[256], base[256]; hist: [256]
-  __shared__ float4 s_geo[4 * 64];
-  __shared__ float4 s_col[4 * 64];
+  __shared__ float4 s_fwd[dev::fwd_lds_float4(4)];
   const int nj = T->njobs;
   const int* U = T->units[PH];
   const int total = U[nj];
@@ -86,10 +85,10 @@ __global__ __launch_bounds__(256) void kj_phase(const JobTable* __restrict__ T) 
       dev::bin_gather(v, local);
     } else if constexpr (PH == PH_FWD) {
       switch (T->ct[lo]) {
-        case 1: dev::forward_tile<1>(v, local, s_geo, s_col); break;
-        case 2: dev::forward_tile<2>(v, local, s_geo, s_col); break;
-        case 3: dev::forward_tile<3>(v, local, s_geo, s_col); break;
-        default: dev::forward_tile<4>(v, local, s_geo, s_col); break;
+        case 1: dev::forward_tile<1>(v, local, s_fwd); break;
+        case 2: dev::forward_tile<2>(v, local, s_fwd); break;
+        case 3: dev::forward_tile<3>(v, local, s_fwd); break;
+        default: dev::forward_tile<4>(v, local, s_fwd); break;
       }
     } else if constexpr (PH == PH_BPIX) {
       switch (T->ct[lo]) {

@@ -49,11 +49,10 @@ __device__ inline int xcd_remap(int bid, int nblocks) {
 template <int CT>
 __global__ __launch_bounds__(256) void k_forward(ImageView v0, int tiles_per_image, int total) {
   constexpr int CS = CT < 4 ? 4 : CT;
-  __shared__ float4 s_geo[4 * 64];
-  __shared__ float4 s_col[4 * 64 * (CS / 4)];
+  __shared__ float4 lds[dev::fwd_lds_float4(CS)];
   const int t = xcd_remap(blockIdx.x, total);
   const int b = t / tiles_per_image;
-  dev::forward_tile<CT>(image_of(v0, b), t - b * tiles_per_image, s_geo, s_col);
+  dev::forward_tile<CT>(image_of(v0, b), t - b * tiles_per_image, lds);
 }
 
 template <int CT>
