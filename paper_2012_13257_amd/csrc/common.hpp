@@ -62,7 +62,7 @@ struct Layout {
   // saved
   size_t Z, reach, offset, perm, geo, col, saved_bytes;
   // workspace
-  size_t binof, keysF, kA, vA, kB, vB, hist, dtot, rpart, prec, gpart, work_bytes;
+  size_t binof, keysF, kA, vA, kB, vB, hist, dtot, rpart, trec, prec, gpart, work_bytes;
 };
 
 inline Layout make_layout(const Geometry& g) {
@@ -86,6 +86,7 @@ inline Layout make_layout(const Geometry& g) {
   L.hist = o;   o = align_up(o + B * size_t(256) * g.ntiles * 4);
   L.dtot = o;   o = align_up(o + B * size_t(256) * 4);
   L.rpart = o;  o = align_up(o + B * size_t(g.units256) * 4 + 4);
+  L.trec = o;   o = align_up(o + B * N * (4 + size_t(g.CS)) * 4);
   L.prec = o;   o = align_up(o + B * HW * size_t(g.CP) * 4);
   L.gpart = o;  o = align_up(o + B * size_t(g.units256) * 4 + 4);
   L.work_bytes = o;
@@ -157,6 +158,7 @@ struct ImageView {
   int* hist;                // [256 * ntiles] per (digit, tile) counts, then offsets
   int* dtot;                // [256] per-digit totals of the current radix pass
   float* rpart;             // [units256] partial maxima of radius*sigma
+  float* trec;              // [N, 4 + CS] packed point records in point order
   float* prec;              // [H, W, CP] backward pixel records
   float* gpart;             // [units256] partial sums of dL/dsigma (shared sigma)
 };
@@ -192,6 +194,7 @@ __host__ __device__ inline ImageView image_of(const ImageView& v0, int b) {
   v.hist = shift(v0.hist, bb * 256 * size_t(v0.ntiles));
   v.dtot = shift(v0.dtot, bb * 256);
   v.rpart = shift(v0.rpart, bb * v0.units256);
+  v.trec = shift(v0.trec, bb * N * (4 + size_t(v0.CS)));
   v.prec = shift(v0.prec, bb * HW * v0.CP);
   v.gpart = shift(v0.gpart, bb * v0.units256);
   return v;
@@ -235,6 +238,7 @@ inline ImageView make_view(const Geometry& g, const Layout& L, void* saved, void
   v.hist = w ? reinterpret_cast<int*>(w + L.hist) : nullptr;
   v.dtot = w ? reinterpret_cast<int*>(w + L.dtot) : nullptr;
   v.rpart = w ? reinterpret_cast<float*>(w + L.rpart) : nullptr;
+  v.trec = w ? reinterpret_cast<float*>(w + L.trec) : nullptr;
   v.prec = w ? reinterpret_cast<float*>(w + L.prec) : nullptr;
   v.gpart = w ? reinterpret_cast<float*>(w + L.gpart) : nullptr;
   return v;

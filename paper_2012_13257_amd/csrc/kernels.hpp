@@ -94,8 +94,22 @@ __device__ inline void bin_keys(const ImageView& v, int unit, float* red4) {
       v.keysF[j] = key;
       v.perm[j] = j;
     }
-    rs = __fmul_rn(v.radius, sigma_of(v, j));
+    const float sg = sigma_of(v, j);
+    rs = __fmul_rn(v.radius, sg);
     if (!(rs >= 0.0f)) rs = 0.0f;  // caller contract violated; keep the reach sane
+    // the point's record (x, y, k, R2, values) packed in point order, so the
+    // gather into bin order reads one record per point
+    float4* rec = reinterpret_cast<float4*>(v.trec + (size_t)j * (4 + v.CS));
+    rec[0] = make_geo(p, sg, v.radius);
+    const float* src = v.values + (size_t)j * v.C;
+    for (int c = 0; c < v.CS; c += 4) {
+      float4 q;
+      q.x = c < v.C ? src[c] : 0.0f;
+      q.y = c + 1 < v.C ? src[c + 1] : 0.0f;
+      q.z = c + 2 < v.C ? src[c + 2] : 0.0f;
+      q.w = c + 3 < v.C ? src[c + 3] : 0.0f;
+      rec[1 + c / 4] = q;
+    }
   }
   const float m = block_max(rs, red4);
   if (threadIdx.x == 0) v.rpart[unit] = m;
@@ -149,12 +163,41 @@ __device__ inline void radix_scan_rows(const ImageView& v, int p, int unit) {
   if (lane == 0) v.dtot[d] = carry;
 }
 
-// unit = one tile: stable scatter of (key, value) by the pass's digit.  Keys
-// are processed in rounds of 256 in index order; within a round, a
-// wavefront ranks equal digits by ballot (multisplit), and the wavefronts
-// are ordered by their index, so equal digits keep their input order.
-__device__ inline void radix_scatter(const ImageView& v, int p, int tile, int* wcnt /*[4][256]*/,
-                                     int* run /*[256]*/, int* base /*[256]*/) {
+// LDS ints radix_scatter needs: wcnt[4][256], run[256], base[256],
+// tstart[256], and the tile's keys and values in digit order.
+__host__ __device__ constexpr int radix_scatter_lds_ints() { return 7 * 256 + 2 * kRadixTile; }
+
+// Exclusive scan of x over the 256 threads of a block (wave scans, then the
+// four wave totals in order).  tmp4: 4 ints of LDS.
+__device__ inline int block_exclusive_scan256(int x, int* tmp4) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int incl = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(incl, o);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) tmp4[wid] = incl;
+  __syncthreads();
+  int pre = 0;
+  for (int w = 0; w < wid; ++w) pre += tmp4[w];
+  __syncthreads();
+  return pre + incl - x;
+}
+
+// unit = one tile: stable scatter of (key, value) by the pass's digit.  The
+// tile's keys are ranked in rounds of 256 in index order; within a round a
+// wavefront ranks equal digits by ballot (multisplit) and the wavefronts are
+// ordered by index, so equal digits keep their input order.  The tile is
+// then laid out in LDS in digit order and written out so that every digit's
+// keys form one contiguous run in the output.
+__device__ inline void radix_scatter(const ImageView& v, int p, int tile, int* lds) {
+  int* wcnt = lds;                 // [4][256]
+  int* run = lds + 1024;           // [256]
+  int* base = lds + 1280;          // [256]
+  int* tstart = lds + 1536;        // [256]
+  int* skey = lds + 1792;          // [kRadixTile]
+  int* sval = skey + kRadixTile;   // [kRadixTile]
   int shift, width;
   radix_pass_bits(v, p, &shift, &width);
   const int ndig = 1 << width, mask = ndig - 1;
@@ -164,33 +207,27 @@ __device__ inline void radix_scatter(const ImageView& v, int p, int tile, int* w
   int* kout = last ? v.keysF : ((p & 1) == 0 ? v.kA : v.kB);
   int* vout = last ? v.perm : ((p & 1) == 0 ? v.vA : v.vB);
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
-  // digit bases: exclusive scan of the digit totals (wave scans, then the
-  // four wave sums in order), plus this tile's offset within its digit
+  const int t0 = tile * kRadixTile;
+  const int tn = min(kRadixTile, v.N - t0);
+  // global start of each digit for this tile: digit base + tile offset
   {
     const int x = t < ndig ? v.dtot[t] : 0;
-    int incl = x;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int y = __shfl_up(incl, o);
-      if (lane >= o) incl += y;
-    }
-    if (lane == 63) wcnt[wid] = incl;
-    __syncthreads();
-    int pre = 0;
-    for (int w = 0; w < wid; ++w) pre += wcnt[w];
-    base[t] = t < ndig ? pre + incl - x + v.hist[t * v.ntiles + tile] : 0;
-    __syncthreads();
+    const int pre = block_exclusive_scan256(x, wcnt);
+    base[t] = t < ndig ? pre + v.hist[t * v.ntiles + tile] : 0;
   }
   run[t] = 0;
   wcnt[t] = 0; wcnt[256 + t] = 0; wcnt[512 + t] = 0; wcnt[768 + t] = 0;
   __syncthreads();
+  // 1) rank of every key among the equal digits of the tile
   const unsigned long long below = (1ull << lane) - 1ull;
+  int key[kRadixItems], val[kRadixItems], rk[kRadixItems];
+#pragma unroll
   for (int r = 0; r < kRadixItems; ++r) {
-    const int idx = tile * kRadixTile + r * 256 + t;
+    const int idx = t0 + r * 256 + t;
     const bool valid = idx < v.N;
-    const int key = valid ? kin[idx] : 0;
-    const int val = valid ? (vin ? vin[idx] : idx) : 0;
-    const int d = (key >> shift) & mask;
+    key[r] = valid ? kin[idx] : 0;
+    val[r] = valid ? (vin ? vin[idx] : idx) : 0;
+    const int d = (key[r] >> shift) & mask;
     unsigned long long peers = __ballot(valid);
     for (int bit = 0; bit < width; ++bit) {
       const bool on = (d >> bit) & 1;
@@ -200,12 +237,9 @@ __device__ inline void radix_scatter(const ImageView& v, int p, int tile, int* w
     const int rank = __popcll(peers & below);
     if (valid && rank == 0) wcnt[wid * 256 + d] = __popcll(peers);
     __syncthreads();
-    if (valid) {
-      int off = base[d] + run[d] + rank;
-      for (int w = 0; w < wid; ++w) off += wcnt[w * 256 + d];
-      kout[off] = key;
-      vout[off] = val;
-    }
+    int off = run[d] + rank;
+    for (int w = 0; w < wid; ++w) off += wcnt[w * 256 + d];
+    rk[r] = valid ? off : -1;
     __syncthreads();
     if (t < ndig) {
       run[t] += wcnt[t] + wcnt[256 + t] + wcnt[512 + t] + wcnt[768 + t];
@@ -213,6 +247,27 @@ __device__ inline void radix_scatter(const ImageView& v, int p, int tile, int* w
     }
     __syncthreads();
   }
+  // 2) the tile in digit order in LDS
+  tstart[t] = block_exclusive_scan256(t < ndig ? run[t] : 0, wcnt);
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRadixItems; ++r) {
+    if (rk[r] >= 0) {
+      const int lpos = tstart[(key[r] >> shift) & mask] + rk[r];
+      skey[lpos] = key[r];
+      sval[lpos] = val[r];
+    }
+  }
+  __syncthreads();
+  // 3) write out: consecutive entries of one digit go to consecutive places
+  for (int e = t; e < tn; e += 256) {
+    const int k = skey[e];
+    const int d = (k >> shift) & mask;
+    const int gpos = base[d] + e - tstart[d];
+    kout[gpos] = k;
+    vout[gpos] = sval[e];
+  }
+  __syncthreads();
 }
 
 // unit = 256 sorted positions (N + 1 positions in all): bin offsets from the
@@ -233,22 +288,16 @@ __device__ inline void bin_finish(const ImageView& v, int unit, float* red4) {
   }
 }
 
-// unit = 256 sorted positions: gather the sorted records and values
+// unit = 256 sorted positions: the sorted records and values, each copied
+// from the packed record of its point
 __device__ inline void bin_gather(const ImageView& v, int unit) {
   const int i = unit * 256 + threadIdx.x;
   if (i >= v.N) return;
   const int j = v.perm[i];
-  v.geo[i] = make_geo(v.pos[j], sigma_of(v, j), v.radius);
-  const float* src = v.values + (size_t)j * v.C;
-  float* dst = v.col + (size_t)i * v.CS;
-  for (int c = 0; c < v.CS; c += 4) {
-    float4 q;
-    q.x = c < v.C ? src[c] : 0.0f;
-    q.y = c + 1 < v.C ? src[c + 1] : 0.0f;
-    q.z = c + 2 < v.C ? src[c + 2] : 0.0f;
-    q.w = c + 3 < v.C ? src[c + 3] : 0.0f;
-    *reinterpret_cast<float4*>(dst + c) = q;
-  }
+  const float4* rec = reinterpret_cast<const float4*>(v.trec + (size_t)j * (4 + v.CS));
+  v.geo[i] = rec[0];
+  float4* dst = reinterpret_cast<float4*>(v.col + (size_t)i * v.CS);
+  for (int c = 0; c < v.CS / 4; ++c) dst[c] = rec[1 + c];
 }
 
 // number of positions bin_finish covers, in units of 256
@@ -270,27 +319,16 @@ __host__ __device__ inline int fwd_tiles(int bx_blocks, int by_blocks) {
   return ((bx_blocks + 1) / 2) * ((by_blocks + 1) / 2);
 }
 
-// float4 elements of LDS a 256-thread forward block needs: per wavefront,
-// 64 candidate records + one sentinel, their values, and four 64-entry lists.
-__host__ __device__ constexpr int fwd_lds_per_wave(int CS) { return 65 + 65 * (CS / 4) + 64; }
-__host__ __device__ constexpr int fwd_lds_float4(int CS) { return 4 * fwd_lds_per_wave(CS); }
-
 // One 256-thread block = one 16x16 pixel tile; wavefront w owns the 8x8
-// block (w & 1, w >> 1) of it, and its four 16-lane quarters own the four
-// 4x4 quadrants of that block (one pixel per lane).  Candidates are the
+// block (w & 1, w >> 1) of it, one pixel per lane.  Candidates are the
 // records of the bins within reach of the block (one contiguous range per
 // bin row), taken 64 at a time: each lane tests one candidate's disk against
-// the four quadrants; candidates reaching any quadrant are staged in LDS and
-// every quadrant gets the list of its own hits, in candidate order (shorter
-// lists are padded with a sentinel record that never passes the radius
-// test).  The quarters then walk their lists in lockstep, every lane
-// evaluating the radius test and the weight for its pixel.  A pixel sums the
-// same nonzero terms in the same (sorted) order as any other split of the
-// work, so the result does not depend on the block shape.
+// the block, the hits are compacted in candidate order into the wavefront's
+// LDS list, and every lane then evaluates each hit for its pixel.
 template <int CT>
-__device__ inline void forward_tile(const ImageView& v, int tile, float4* lds) {
+__device__ inline void forward_tile(const ImageView& v, int tile, float4* s_geo /*[4][64]*/,
+                                    float4* s_col /*[4][64*CS/4]*/) {
   constexpr int CS = CT < 4 ? 4 : CT;
-  constexpr int Q = CS / 4;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int wgx = fwd_tiles_x(v.bx_blocks);
   const int ty = tile / wgx, tx = tile - ty * wgx;
@@ -299,26 +337,8 @@ __device__ inline void forward_tile(const ImageView& v, int tile, float4* lds) {
   if (u0 >= v.W || v0 >= v.H) return;
   const int ue = min(u0 + kBlockSide - 1, v.W - 1);
   const int ve = min(v0 + kBlockSide - 1, v.H - 1);
-  const int q = lane >> 4, pq = lane & 15;
-  const int u = u0 + (q & 1) * 4 + (pq & 3);
-  const int vv = v0 + (q >> 1) * 4 + (pq >> 2);
+  const int u = u0 + (lane & 7), vv = v0 + (lane >> 3);
   const float fu = (float)u, fv = (float)vv;
-  // quadrant bounds, clipped to the image (an empty right / bottom pair is
-  // marked by a lower bound above the upper one)
-  const float xl0 = (float)u0, xl1 = (float)min(u0 + 3, ue);
-  const float xr0 = (float)(u0 + 4), xr1 = (float)min(u0 + 7, ue);
-  const float yt0 = (float)v0, yt1 = (float)min(v0 + 3, ve);
-  const float yb0 = (float)(v0 + 4), yb1 = (float)min(v0 + 7, ve);
-  const bool has_r = u0 + 4 <= ue, has_b = v0 + 4 <= ve;
-
-  float4* cgeo = lds + wid * fwd_lds_per_wave(CS);
-  float4* ccol = cgeo + 65;
-  int* lists = reinterpret_cast<int*>(ccol + 65 * Q);  // [4][64]
-  if (lane == 0) {
-    cgeo[64] = make_float4(0.0f, 0.0f, 0.0f, -1.0f);  // sentinel: R2 < 0 never passes
-#pragma unroll
-    for (int k = 0; k < Q; ++k) ccol[64 * Q + k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-  }
 
   // float math runs on the vector ALU; readfirstlane keeps the wave-uniform
   // loop bounds in scalar registers
@@ -328,66 +348,48 @@ __device__ inline void forward_tile(const ImageView& v, int tile, float4* lds) {
   const int by_lo = __builtin_amdgcn_readfirstlane(bin_coord((float)v0 - Rh, v.inv_tile, v.nby));
   const int by_hi = __builtin_amdgcn_readfirstlane(bin_coord((float)ve + Rh, v.inv_tile, v.nby));
   const float4* gb = v.geo;
-  const float4* cb = reinterpret_cast<const float4*>(v.col);
+  const float* cb = v.col;
 
   float Z = 0.0f;
   float acc[CT];
 #pragma unroll
   for (int k = 0; k < CT; ++k) acc[k] = 0.0f;
-  const int* mylist = lists + q * 64;
+
+  float4* lgeo = s_geo + wid * 64;
+  float4* lcol = s_col + wid * 64 * (CS / 4);
 
   for (int by = by_lo; by <= by_hi; ++by) {
     const int s = __builtin_amdgcn_readfirstlane(v.offset[by * v.nbx + bx_lo]);
     const int e = __builtin_amdgcn_readfirstlane(v.offset[by * v.nbx + bx_hi + 1]);
     for (int c0 = s; c0 < e; c0 += 64) {
       const int jc = c0 + lane;
-      bool h0 = false, h1 = false, h2 = false, h3 = false;
+      bool hit = false;
       float4 g = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       if (jc < e) {
         g = gb[jc];
-        // distance from the disk centre to each quadrant (conservative test)
-        const float exl = fmaxf(fmaxf(xl0 - g.x, g.x - xl1), 0.0f);
-        const float exr = has_r ? fmaxf(fmaxf(xr0 - g.x, g.x - xr1), 0.0f) : 1e30f;
-        const float eyt = fmaxf(fmaxf(yt0 - g.y, g.y - yt1), 0.0f);
-        const float eyb = has_b ? fmaxf(fmaxf(yb0 - g.y, g.y - yb1), 0.0f) : 1e30f;
-        const float lim = g.w * 1.001f + 1e-6f;
-        h0 = exl * exl + eyt * eyt <= lim;
-        h1 = exr * exr + eyt * eyt <= lim;
-        h2 = exl * exl + eyb * eyb <= lim;
-        h3 = exr * exr + eyb * eyb <= lim;
+        const float ex = fmaxf(fmaxf((float)u0 - g.x, g.x - (float)ue), 0.0f);
+        const float ey = fmaxf(fmaxf((float)v0 - g.y, g.y - (float)ve), 0.0f);
+        hit = ex * ex + ey * ey <= g.w * 1.001f + 1e-6f;
       }
-      const bool any = h0 || h1 || h2 || h3;
-      const unsigned long long many = __ballot(any);
-      if (many == 0) continue;
-      const int slot = __builtin_amdgcn_mbcnt_hi((unsigned)(many >> 32),
-                                                 __builtin_amdgcn_mbcnt_lo((unsigned)many, 0));
-      if (any) {
-        cgeo[slot] = g;
+      const unsigned long long mask = __ballot(hit);
+      if (mask == 0) continue;
+      if (hit) {
+        const int slot = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                                   __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0));
+        lgeo[slot] = g;
+        const float4* cp = reinterpret_cast<const float4*>(cb + (size_t)jc * CS);
 #pragma unroll
-        for (int k = 0; k < Q; ++k) ccol[slot * Q + k] = cb[(size_t)jc * Q + k];
+        for (int q = 0; q < CS / 4; ++q) lcol[slot * (CS / 4) + q] = cp[q];
       }
-      const unsigned long long m0 = __ballot(h0), m1 = __ballot(h1);
-      const unsigned long long m2 = __ballot(h2), m3 = __ballot(h3);
-      const int n0 = __popcll(m0), n1 = __popcll(m1), n2 = __popcll(m2), n3 = __popcll(m3);
-      const int nmax = max(max(n0, n1), max(n2, n3));
-#define GMM_LIST_PUT(qq, mq, hq, nq)                                                          \
-      if (hq) lists[qq * 64 + __builtin_amdgcn_mbcnt_hi((unsigned)(mq >> 32),                 \
-                    __builtin_amdgcn_mbcnt_lo((unsigned)mq, 0))] = slot;                       \
-      if (lane >= nq && lane < nmax) lists[qq * 64 + lane] = 64;
-      GMM_LIST_PUT(0, m0, h0, n0)
-      GMM_LIST_PUT(1, m1, h1, n1)
-      GMM_LIST_PUT(2, m2, h2, n2)
-      GMM_LIST_PUT(3, m3, h3, n3)
-#undef GMM_LIST_PUT
       wave_lds_sync();
-      for (int i = 0; i < nmax; ++i) {
-        const int idx = mylist[i];
-        const float4 r = cgeo[idx];
+      const int nh = __popcll(mask);
+      for (int i = 0; i < nh; ++i) {
+        const float4 r = lgeo[i];
         float cc[CS];
 #pragma unroll
-        for (int k = 0; k < Q; ++k) {
-          const float4 tq = ccol[idx * Q + k];
-          cc[4 * k] = tq.x; cc[4 * k + 1] = tq.y; cc[4 * k + 2] = tq.z; cc[4 * k + 3] = tq.w;
+        for (int q = 0; q < CS / 4; ++q) {
+          const float4 tq = lcol[i * (CS / 4) + q];
+          cc[4 * q] = tq.x; cc[4 * q + 1] = tq.y; cc[4 * q + 2] = tq.z; cc[4 * q + 3] = tq.w;
         }
         // radius test exactly as specified: float32, every operation rounded
         const float dx = fu - r.x;
@@ -450,14 +452,45 @@ __device__ inline void bwd_pixel(const ImageView& v, int unit) {
     dst[q] = make_float4(rec[4 * q], rec[4 * q + 1], rec[4 * q + 2], rec[4 * q + 3]);
 }
 
-// unit = 256 points in sorted order.  Each thread walks its point's disk
-// bounding box, repeats the forward's radius test bit for bit, recomputes
-// w_ij and accumulates in registers; results go to the point's own index.
+// unit = 256 points in sorted order.  The block first regroups its points by
+// the size of their disk (so the lanes of a wavefront loop over similar
+// extents); each thread then walks its point's disk row by row -- the columns
+// of a row bounded by a conservative chord and visited without branching
+// (pixels outside the radius get w = 0, so the loads can be issued ahead),
+// the forward's radius test repeated bit for bit -- recomputes w_ij and
+// accumulates in registers; results go to the point's own index.  A point's
+// result does not depend on which lane computes it, and the shared-sigma
+// partial sum is taken in the original point order: the output is
+// deterministic.  lds: 256 + 32 ints.
 template <int CT>
-__device__ inline void bwd_point(const ImageView& v, int unit, float* red4) {
+__device__ inline void bwd_point(const ImageView& v, int unit, float* red4, int* lds) {
   constexpr int CS = CT < 4 ? 4 : CT;
   constexpr int CP = (CT + 1 + 3) / 4 * 4;
-  const int t = unit * 256 + threadIdx.x;
+  int* order = lds;            // [256] local point index by regrouped slot
+  int* cls_n = lds + 256;      // [32]
+  float* gs_l = reinterpret_cast<float*>(lds);
+  const int base = unit * 256;
+  {
+    const int tt = base + threadIdx.x;
+    int cls = 0;
+    if (tt < v.N) {
+      const float4 gg = v.geo[tt];
+      cls = min(31, 1 + (int)fminf(2.0f * sqrtf(fmaxf(gg.w, 0.0f)), 30.0f));
+    }
+    if (threadIdx.x < 32) cls_n[threadIdx.x] = 0;
+    __syncthreads();
+    const int slot = atomicAdd(&cls_n[cls], 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int run = 0;
+      for (int c = 0; c < 32; ++c) { const int n = cls_n[c]; cls_n[c] = run; run += n; }
+    }
+    __syncthreads();
+    order[cls_n[cls] + slot] = threadIdx.x;
+    __syncthreads();
+  }
+  const int lp = order[threadIdx.x];
+  const int t = base + lp;
   float gsig = 0.0f;
   if (t < v.N) {
     const float4 g = v.geo[t];
@@ -478,33 +511,39 @@ __device__ inline void bwd_point(const ImageView& v, int unit, float* red4) {
     float gc[CT];
 #pragma unroll
     for (int k = 0; k < CT; ++k) gc[k] = 0.0f;
+    const float R2m = g.w * (1.0f + 0x1p-20f);
     for (int py = vlo; py <= vhi; ++py) {
       const float dy = (float)py - g.y;
       const float dyy = dy * dy;
-      const float* prow = v.prec + (size_t)py * v.W * CP;
+      // conservative chord of the disk on this row; every pixel of it is
+      // visited without branching (pixels outside the radius get w = 0)
+      const float rr = sqrtf(fmaxf(R2m - dyy, 0.0f)) * (1.0f + 0x1p-10f) + 0x1p-10f;
+      const float fulo = fminf(fmaxf(ceilf(g.x - rr), 0.0f), (float)v.W);
+      const float fuhi = fmaxf(fminf(floorf(g.x + rr), (float)(v.W - 1)), -1.0f);
+      const int ulo = (int)fulo, uhi = (int)fuhi;
+      const float4* prow = reinterpret_cast<const float4*>(v.prec + (size_t)py * v.W * CP);
+#pragma unroll 4
       for (int px = ulo; px <= uhi; ++px) {
         const float dx = (float)px - g.x;
         const float d2 = dx * dx + dyy;
-        if (d2 <= g.w) {
-          const float w = __builtin_amdgcn_exp2f(d2 * g.z);
-          const float4* rp = reinterpret_cast<const float4*>(prow + (size_t)px * CP);
-          float rec[CP];
+        float rec[CP];
 #pragma unroll
-          for (int q = 0; q < CP / 4; ++q) {
-            const float4 r4 = rp[q];
-            rec[4 * q] = r4.x; rec[4 * q + 1] = r4.y; rec[4 * q + 2] = r4.z; rec[4 * q + 3] = r4.w;
-          }
-          float A = -rec[CT];
-#pragma unroll
-          for (int k = 0; k < CT; ++k) {
-            A = __builtin_fmaf(rec[k], cc[k], A);
-            gc[k] = __builtin_fmaf(w, rec[k], gc[k]);
-          }
-          const float tA = A * w;
-          gx = __builtin_fmaf(tA, dx, gx);
-          gy = __builtin_fmaf(tA, dy, gy);
-          gs = __builtin_fmaf(tA, d2, gs);
+        for (int q = 0; q < CP / 4; ++q) {
+          const float4 r4 = prow[(size_t)px * (CP / 4) + q];
+          rec[4 * q] = r4.x; rec[4 * q + 1] = r4.y; rec[4 * q + 2] = r4.z; rec[4 * q + 3] = r4.w;
         }
+        float w = __builtin_amdgcn_exp2f(d2 * g.z);
+        w = (d2 <= g.w) ? w : 0.0f;
+        float A = -rec[CT];
+#pragma unroll
+        for (int k = 0; k < CT; ++k) {
+          A = __builtin_fmaf(rec[k], cc[k], A);
+          gc[k] = __builtin_fmaf(w, rec[k], gc[k]);
+        }
+        const float tA = A * w;
+        gx = __builtin_fmaf(tA, dx, gx);
+        gy = __builtin_fmaf(tA, dy, gy);
+        gs = __builtin_fmaf(tA, d2, gs);
       }
     }
     const float inv_s2 = 1.0f / (sg * sg);
@@ -518,7 +557,10 @@ __device__ inline void bwd_point(const ImageView& v, int unit, float* red4) {
     }
   }
   if (!v.per_point && v.grad_sigma) {
-    const float s = block_sum(gsig, red4);
+    __syncthreads();
+    gs_l[lp] = gsig;
+    __syncthreads();
+    const float s = block_sum(gs_l[threadIdx.x], red4);
     if (threadIdx.x == 0) v.gpart[unit] = s;
   }
 }

@@ -55,11 +55,22 @@ struct JobTable {
 // Job-table kernels
 // ---------------------------------------------------------------------------
 
+// LDS of each phase kernel: only what its phase uses
+template <int PH>
+struct PhaseLds {
+  static constexpr int ints = (PH >= PH_SCAT0 && PH <= PH_SCAT2) ? dev::radix_scatter_lds_ints()
+                              : (PH == PH_BPOINT)                 ? 256 + 64
+                              : (PH >= PH_HIST0 && PH <= PH_HIST2) ? 256
+                                                                  : 4;
+  static constexpr int f4 = PH == PH_FWD ? 4 * 64 : 1;
+};
+
 template <int PH>
 __global__ __launch_bounds__(256) void kj_phase(const JobTable* __restrict__ T) {
   __shared__ float red4[4];
-  __shared__ int lds_i[6 * 256];   // radix: wcnt[4*256], run[256], base[256]; hist: [256]
-  __shared__ float4 s_fwd[dev::fwd_lds_float4(4)];
+  __shared__ int lds_i[PhaseLds<PH>::ints];
+  __shared__ float4 s_geo[PhaseLds<PH>::f4];
+  __shared__ float4 s_col[PhaseLds<PH>::f4];
   const int nj = T->njobs;
   const int* U = T->units[PH];
   const int total = U[nj];
@@ -78,17 +89,17 @@ __global__ __launch_bounds__(256) void kj_phase(const JobTable* __restrict__ T) 
     } else if constexpr (PH >= PH_SCAN0 && PH <= PH_SCAN2) {
       dev::radix_scan_rows(v, PH - PH_SCAN0, local);
     } else if constexpr (PH >= PH_SCAT0 && PH <= PH_SCAT2) {
-      dev::radix_scatter(v, PH - PH_SCAT0, local, lds_i, lds_i + 1024, lds_i + 1280);
+      dev::radix_scatter(v, PH - PH_SCAT0, local, lds_i);
     } else if constexpr (PH == PH_FINISH) {
       dev::bin_finish(v, local, red4);
     } else if constexpr (PH == PH_GATHER) {
       dev::bin_gather(v, local);
     } else if constexpr (PH == PH_FWD) {
       switch (T->ct[lo]) {
-        case 1: dev::forward_tile<1>(v, local, s_fwd); break;
-        case 2: dev::forward_tile<2>(v, local, s_fwd); break;
-        case 3: dev::forward_tile<3>(v, local, s_fwd); break;
-        default: dev::forward_tile<4>(v, local, s_fwd); break;
+        case 1: dev::forward_tile<1>(v, local, s_geo, s_col); break;
+        case 2: dev::forward_tile<2>(v, local, s_geo, s_col); break;
+        case 3: dev::forward_tile<3>(v, local, s_geo, s_col); break;
+        default: dev::forward_tile<4>(v, local, s_geo, s_col); break;
       }
     } else if constexpr (PH == PH_BPIX) {
       switch (T->ct[lo]) {
@@ -99,10 +110,10 @@ __global__ __launch_bounds__(256) void kj_phase(const JobTable* __restrict__ T) 
       }
     } else if constexpr (PH == PH_BPOINT) {
       switch (T->ct[lo]) {
-        case 1: dev::bwd_point<1>(v, local, red4); break;
-        case 2: dev::bwd_point<2>(v, local, red4); break;
-        case 3: dev::bwd_point<3>(v, local, red4); break;
-        default: dev::bwd_point<4>(v, local, red4); break;
+        case 1: dev::bwd_point<1>(v, local, red4, lds_i); break;
+        case 2: dev::bwd_point<2>(v, local, red4, lds_i); break;
+        case 3: dev::bwd_point<3>(v, local, red4, lds_i); break;
+        default: dev::bwd_point<4>(v, local, red4, lds_i); break;
       }
     } else if constexpr (PH == PH_BSIG) {
       dev::bwd_sigma_sum(v, red4);

@@ -22,10 +22,8 @@ __global__ __launch_bounds__(256) void k_radix_scan(ImageView v0, int p) {
 }
 
 __global__ __launch_bounds__(256) void k_radix_scatter(ImageView v0, int p) {
-  __shared__ int wcnt[4 * 256];
-  __shared__ int run[256];
-  __shared__ int base[256];
-  dev::radix_scatter(image_of(v0, blockIdx.y), p, blockIdx.x, wcnt, run, base);
+  __shared__ int lds[dev::radix_scatter_lds_ints()];
+  dev::radix_scatter(image_of(v0, blockIdx.y), p, blockIdx.x, lds);
 }
 
 __global__ __launch_bounds__(256) void k_bin_finish(ImageView v0) {
@@ -37,22 +35,20 @@ __global__ __launch_bounds__(256) void k_bin_gather(ImageView v0) {
   dev::bin_gather(image_of(v0, blockIdx.y), blockIdx.x);
 }
 
-// Workgroups are dispatched round-robin over the 8 XCDs; give every XCD a
-// contiguous range of tiles so that neighbouring tiles (which read the same
-// halo records) share one L2.
-__device__ inline int xcd_remap(int bid, int nblocks) {
-  const int xcd = bid & 7, idx = bid >> 3;
-  const int per = nblocks >> 3, rem = nblocks & 7;
-  return xcd * per + min(xcd, rem) + idx;
-}
-
+// Tiles are taken in row-major order, so consecutive workgroups -- which the
+// dispatcher spreads round-robin over the 8 XCDs -- interleave over the image
+// and every XCD gets a share of the dense and of the sparse regions.  (Giving
+// each XCD a contiguous band of tiles keeps halo reads in one L2 but leaves
+// the XCDs that own dense bands running long after the others: measured
+// slower on clustered point sets.)
 template <int CT>
-__global__ __launch_bounds__(256) void k_forward(ImageView v0, int tiles_per_image, int total) {
+__global__ __launch_bounds__(256) void k_forward(ImageView v0, int tiles_per_image) {
   constexpr int CS = CT < 4 ? 4 : CT;
-  __shared__ float4 lds[dev::fwd_lds_float4(CS)];
-  const int t = xcd_remap(blockIdx.x, total);
+  __shared__ float4 s_geo[4 * 64];
+  __shared__ float4 s_col[4 * 64 * (CS / 4)];
+  const int t = blockIdx.x;
   const int b = t / tiles_per_image;
-  dev::forward_tile<CT>(image_of(v0, b), t - b * tiles_per_image, lds);
+  dev::forward_tile<CT>(image_of(v0, b), t - b * tiles_per_image, s_geo, s_col);
 }
 
 template <int CT>
@@ -63,7 +59,8 @@ __global__ __launch_bounds__(256) void k_bwd_pixel(ImageView v0) {
 template <int CT>
 __global__ __launch_bounds__(256) void k_bwd_point(ImageView v0) {
   __shared__ float red4[4];
-  dev::bwd_point<CT>(image_of(v0, blockIdx.y), blockIdx.x, red4);
+  __shared__ int lds[256 + 64];
+  dev::bwd_point<CT>(image_of(v0, blockIdx.y), blockIdx.x, red4, lds);
 }
 
 __global__ __launch_bounds__(256) void k_bwd_sigma_sum(ImageView v0) {
@@ -85,7 +82,7 @@ hipError_t launch_forward_t(const Geometry& g, const ImageView& v0, hipStream_t 
   const long long total = (long long)per * g.B;
   if (total >= (1LL << 31)) return hipErrorInvalidValue;
   ProfRange pr_("forward", st);
-  hipLaunchKernelGGL(k_forward<CT>, dim3((unsigned)total), dim3(256), 0, st, v0, per, (int)total);
+  hipLaunchKernelGGL(k_forward<CT>, dim3((unsigned)total), dim3(256), 0, st, v0, per);
   return hipSuccess;
 }
 
