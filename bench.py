@@ -35,6 +35,34 @@ VALU_PEAK_TLANEOPS = CU * SIMD_LANES_PER_CU * CLOCK_GHZ / 1000.0   # 39.32 T lan
 #            1 select, 1 add (Z), C FMAs                       = 10 + C
 #   backward 1 sub + 1 mul + 1 add (d2, the row term amortised), 1 cmp,
 #            1 mul, 1 exp, C FMAs (A), C FMAs (dL/dc), 1 mul, 3 FMAs = 11 + 2C
+FORWARD_SOURCES = ("common.hpp", "kernels.hpp", "single.hip")
+FORWARD_PROFILE = os.path.join(ROOT, "profiles", "forward_1024x1024_n1M_c3.md")
+
+
+def forward_source_hash() -> str:
+    """sha256 of the sources the forward kernel is built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in FORWARD_SOURCES:
+        with open(os.path.join(ROOT, "paper_2012_13257_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def forward_traffic():
+    """HBM bytes per forward launch from the committed counter summary, or None
+    when the forward's sources changed since the counters were taken."""
+    try:
+        with open(FORWARD_PROFILE) as fh:
+            kv = dict(line.split(": ", 1) for line in fh.read().splitlines()
+                      if line.startswith("forward_") and ": " in line)
+        if kv.get("forward_source_sha256", "").strip() != forward_source_hash():
+            return None
+        return int(kv["forward_fetch_bytes_per_launch"]) + int(kv["forward_write_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def fwd_ops(C):
     return 10 + C
 
@@ -109,6 +137,21 @@ def time_steps(fn, steps: int, warmup: int, profile: bool):
                 kernels[name] = {"avg_us": 1000.0 * tot / n, "launches": n}
         _lib.profile_enable(False)
     return ms, wall, kernels
+
+
+def capture(fn):
+    """Captures fn's launches (issued on torch's current stream) into a HIP graph."""
+    import torch
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    torch.cuda.synchronize()
+    return g
 
 
 def cpu_baseline(wl, G, budget_s: float):
@@ -351,30 +394,49 @@ def main():
     gp = torch.empty_like(pos)
     gs = torch.empty_like(sig)
     gv = torch.empty_like(val)
-    stream = torch.cuda.current_stream().cuda_stream
     pb = ctypes.byref(prob)
 
     def fwd():
+        st = torch.cuda.current_stream().cuda_stream
         _lib.check("interp_forward", L.interp_forward(
             pb, pos.data_ptr(), sig.data_ptr(), val.data_ptr(), out.data_ptr(), saved.addr,
-            saved.nbytes, work.addr, work.nbytes, stream))
+            saved.nbytes, work.addr, work.nbytes, st))
 
     def bwd():
+        st = torch.cuda.current_stream().cuda_stream
         _lib.check("interp_backward", L.interp_backward(
             pb, pos.data_ptr(), sig.data_ptr(), val.data_ptr(), out.data_ptr(), saved.addr,
             saved.nbytes, G.data_ptr(), gp.data_ptr(), gs.data_ptr(), gv.data_ptr(), work.addr,
-            work.nbytes, stream))
+            work.nbytes, st))
 
     def step():
         fwd()
         bwd()
 
-    ms_step, wall, kernels = time_steps(step, args.steps, args.warmup, profile=True)
-    log(f"fwd+bwd {ms_step * 1e3:.1f} us/step (wall {wall / args.steps * 1e6:.1f} us/step)")
-    ms_fwd, _, kernels_fwd = time_steps(fwd, args.steps, args.warmup, profile=True)
-    log(f"fwd {ms_fwd * 1e3:.1f} us/step")
+    # eager: one C-ABI call per forward / backward, no per-kernel events
+    ms_eager, wall, _ = time_steps(step, args.steps, args.warmup, profile=False)
+    log(f"fwd+bwd eager {ms_eager * 1e3:.1f} us/step (wall {wall / args.steps * 1e6:.1f} us/step)")
+    ref = [t.clone() for t in (out, gp, gs, gv)]
+    ms_fwd_eager, _, _ = time_steps(fwd, args.steps, args.warmup, profile=False)
+    # the same calls captured once into a HIP graph and replayed
+    graph, graph_fwd = capture(step), capture(fwd)
+    ms_graph, _, _ = time_steps(graph.replay, args.steps, args.warmup, profile=False)
+    step()
+    torch.cuda.synchronize()
+    graph.replay()
+    torch.cuda.synchronize()
+    graph_ok = all(torch.equal(a, b) for a, b in zip(ref, (out, gp, gs, gv)))
+    ms_fwd_graph, _, _ = time_steps(graph_fwd.replay, args.steps, args.warmup, profile=False)
+    log(f"fwd+bwd graph {ms_graph * 1e3:.1f} us/step, fwd eager {ms_fwd_eager * 1e3:.1f} "
+        f"graph {ms_fwd_graph * 1e3:.1f}; graph replay bitwise equal to eager: {graph_ok}")
+    if not graph_ok:
+        raise RuntimeError("graph replay differs from the eager result")
+    # per-kernel durations: a separate run with events around every launch
+    _, _, kernels = time_steps(step, args.steps, args.warmup, profile=True)
     for k, v in kernels.items():
         log(f"  {k:16s} {v['avg_us']:9.2f} us x{v['launches']}")
+    ms_step = min(ms_eager, ms_graph)
+    ms_fwd = min(ms_fwd_eager, ms_fwd_graph)
 
     pix = wl.B * wl.H * wl.W
     value = pix / (ms_step * 1e-3) / 1e6
@@ -399,7 +461,8 @@ def main():
         achieved = work_units / (info["avg_us"] * 1e-6) / 1e12
         roof = {"bound": "alu", "kernel": name, "achieved": round(achieved, 3),
                 "peak": round(VALU_PEAK_TLANEOPS, 2), "unit": "Tlaneop/s",
-                "frac": round(achieved / VALU_PEAK_TLANEOPS, 4), "traffic": None,
+                "frac": round(achieved / VALU_PEAK_TLANEOPS, 4),
+                "traffic": forward_traffic() if name == "forward" else None,
                 "work_per_launch": f"P={P} pairs x {ops_fwd_pair if name == 'forward' else ops_bwd_pair} "
                                    "VALU lane-ops",
                 "kernel_avg_us": round(info["avg_us"], 2)}
@@ -428,6 +491,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4),
+        "launch": "hip_graph" if ms_graph <= ms_eager else "eager",
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -438,6 +502,10 @@ def main():
                    "pairs_in_radius": P},
         "fwd_mpix_s": round(fwd_mpix, 2),
         "fwd_ms": round(ms_fwd, 4),
+        "eager_ms_per_step": round(ms_eager, 4),
+        "graph_ms_per_step": round(ms_graph, 4),
+        "fwd_eager_ms": round(ms_fwd_eager, 4),
+        "fwd_graph_ms": round(ms_fwd_graph, 4),
         "kernels_us": {k: round(v["avg_us"], 2) for k, v in kernels.items()},
         "kernel_alu": other,
         "roofline": roof,

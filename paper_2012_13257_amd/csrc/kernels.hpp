@@ -16,7 +16,8 @@
 //   bin_finish     bin offsets from the sorted keys; per-image reach
 //   bin_gather     sorted point records (x, y, k, R2) and values
 //   forward        the gather: per 8x8 pixel block, candidates from the bins
-//                  within reach, culled per wavefront, hits evaluated per pixel
+//                  within reach, culled per 4x4 quarter of the block, hits
+//                  evaluated per pixel (units numbered XCD-aware)
 // Backward (quotient rule on Eq. 1; formulas in include/gmminterp.h):
 //   bwd_pixel      G'_ik = G_ik / Z_i and beta_i per pixel
 //   bwd_point      per point: walk its disk's bounding box, recompute w_ij,
@@ -413,6 +414,245 @@ __device__ inline void forward_tile(const ImageView& v, int tile, float4* s_geo 
       if (k < v.C) v.out[k * HW + pix] = Z > 0.0f ? acc[k] / Z : 0.0f;
     }
     v.Z[pix] = Z;
+  }
+}
+
+// Forward gather for up to 4 channels.  A wavefront evaluates one 8x8 pixel
+// block; a block's candidates are the records of the bins within reach --
+// one contiguous range of the sorted order per bin row -- taken as a single
+// concatenated sequence in 64-record chunks, and the kSplit wavefronts that
+// share a block take chunks w, w + kSplit, ... of it (a dense block is spread
+// over several SIMDs).  Within a wavefront the block is cut into four 4x4
+// quarters: each candidate is tested against every quarter and appended to
+// the LDS list of each quarter its disk reaches, and a quarter's list is
+// evaluated four candidates at a time -- lane group g = lane / 16 takes list
+// entries g, g+4, ... for pixel lane % 16 of the quarter (lists are padded to
+// a multiple of four with a null record: w = 0, values 0).  The next chunk's
+// records are loaded while the current one is processed.  Partial sums are
+// combined in a fixed order: the lane groups of a quarter as (g0 + g1) +
+// (g2 + g3), then the wavefronts of a block likewise.
+constexpr int kQuarterList = 68;  // 64 hits + up to 3 padding entries
+constexpr int kFwdSplit = 2;      // wavefronts per 8x8 block
+__host__ __device__ inline constexpr int fwd_quarter_lds_f4() {
+  return 4 * 4 * kQuarterList * 2;  // waves x quarters x entries x (geo, values)
+}
+
+// Forward work units.  A unit (one 256-thread block) covers UBW x UBH blocks
+// of 8x8 pixels.  The dispatcher hands consecutive workgroups to the 8 XCDs
+// in turn, so unit number i runs on XCD i % 8: units are numbered in groups
+// of 8 that tile a 4 x 2 patch of units, and each XCD gets the same position
+// in every patch -- a regular lattice over the image, so a dense region is
+// shared by all XCDs instead of loading the few that own its columns.
+constexpr int kUBW = kFwdSplit == 1 ? 2 : kFwdSplit == 2 ? 2 : 1;
+constexpr int kUBH = kFwdSplit == 1 ? 2 : 1;
+struct FwdUnits {
+  int ux, uy, stx;  // units per row / column, 4x2 patches per row
+  __host__ __device__ FwdUnits(int bx_blocks, int by_blocks)
+      : ux((bx_blocks + kUBW - 1) / kUBW), uy((by_blocks + kUBH - 1) / kUBH), stx((ux + 3) / 4) {}
+  __host__ __device__ int count() const { return stx * ((uy + 1) / 2) * 8; }
+  // unit number -> unit coordinates; false for the padding units of the patches
+  __host__ __device__ bool coords(int unit, int* cx, int* cy) const {
+    const int st = unit >> 3, x = unit & 7;
+    const int sy = st / stx;
+    *cx = 4 * (st - sy * stx) + (x & 3);
+    *cy = 2 * sy + (x >> 2);
+    return *cx < ux && *cy < uy;
+  }
+};
+__host__ __device__ inline int fwd_units(int bx_blocks, int by_blocks) {
+  return FwdUnits(bx_blocks, by_blocks).count();
+}
+
+template <int CT>
+__device__ inline void forward_block_q(const ImageView& v, int unit, float4* s_rec) {
+  static_assert(CT <= 4, "the quarter lists hold the values of a record in one float4");
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int grp = lane >> 4, p = lane & 15;
+  const int sb = wid / kFwdSplit;  // this wavefront's block within the unit
+  const int phase = wid % kFwdSplit;
+  int ucx, ucy;
+  const bool in_grid = FwdUnits(v.bx_blocks, v.by_blocks).coords(unit, &ucx, &ucy);
+  const int bxb = ucx * kUBW + sb % kUBW, byb = ucy * kUBH + sb / kUBW;
+  const bool active = in_grid && bxb < v.bx_blocks && byb < v.by_blocks;
+  const int u0 = (active ? bxb : 0) * kBlockSide;
+  const int v0 = (active ? byb : 0) * kBlockSide;
+  const int ue = min(u0 + kBlockSide - 1, v.W - 1);
+  const int ve = min(v0 + kBlockSide - 1, v.H - 1);
+
+  // quarter boxes: columns [u0, ul] and [u0 + 4, ur], rows [v0, vt] and [v0 + 4, vb]
+  const float fu0 = (float)u0, fv0 = (float)v0;
+  const float ful = (float)min(u0 + 3, ue), fur0 = (float)(u0 + 4), fure = (float)ue;
+  const float fvt = (float)min(v0 + 3, ve), fvb0 = (float)(v0 + 4), fvbe = (float)ve;
+  const bool has_r = u0 + 4 <= ue, has_b = v0 + 4 <= ve;
+  // this lane's pixel in quarter q: (u0 + 4 (q & 1) + p % 4, v0 + 4 (q >> 1) + p / 4)
+  const float pu = fu0 + (float)(p & 3), pv = fv0 + (float)(p >> 2);
+
+  const float Rh = conservative_reach(v.reach[0]);
+  const int bx_lo = __builtin_amdgcn_readfirstlane(bin_coord(fu0 - Rh, v.inv_tile, v.nbx));
+  const int bx_hi = __builtin_amdgcn_readfirstlane(bin_coord((float)ue + Rh, v.inv_tile, v.nbx));
+  const int by_lo = __builtin_amdgcn_readfirstlane(bin_coord(fv0 - Rh, v.inv_tile, v.nby));
+  const int by_hi = active ? __builtin_amdgcn_readfirstlane(bin_coord((float)ve + Rh, v.inv_tile, v.nby))
+                           : by_lo - 1;
+  const float4* gb = v.geo;
+  const float4* cb = reinterpret_cast<const float4*>(v.col);
+
+  float Z[4], acc[4][CT];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    Z[q] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < CT; ++k) acc[q][k] = 0.0f;
+  }
+
+  float4* lst = s_rec + wid * (4 * kQuarterList * 2);
+  const float4 null_geo = make_float4(0.0f, 0.0f, 0.0f, -1.0f);
+  const float4 zero4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+
+  // bin rows in groups of 64 (one row per lane)
+  for (int rg = by_lo; rg <= by_hi; rg += 64) {
+    const int nr = min(64, by_hi - rg + 1);
+    int s_r = 0, len = 0;
+    if (lane < nr) {
+      const int* o = v.offset + (size_t)(rg + lane) * v.nbx;
+      s_r = o[bx_lo];
+      len = o[bx_hi + 1] - s_r;
+    }
+    int incl = len;  // inclusive scan of the row lengths over the lanes
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(incl, o);
+      if (lane >= o) incl += y;
+    }
+    const int total = __builtin_amdgcn_readlane(incl, 63);
+    // record index of position t of the concatenation (t < total): the row r
+    // with excl_r <= t < incl_r, index s_r + t - excl_r
+    auto record_of = [&](int t) {
+      int base = 0;
+      for (int r = 0; r < nr; ++r) {
+        const int ex = __builtin_amdgcn_readlane(incl - len, r);
+        const int sb = __builtin_amdgcn_readlane(s_r, r);
+        base = t >= ex ? sb - ex : base;
+      }
+      return base + t;
+    };
+
+    int c0 = phase * 64;
+    float4 g_n = zero4, c_n = zero4;
+    if (c0 + lane < total) {
+      const int j = record_of(c0 + lane);
+      g_n = gb[j];
+      c_n = cb[j];
+    }
+    for (; c0 < total; c0 += 64 * kFwdSplit) {
+      const bool in = c0 + lane < total;
+      const float4 g = g_n, c = c_n;
+      const int cn = c0 + 64 * kFwdSplit;
+      if (cn + lane < total) {
+        const int j = record_of(cn + lane);
+        g_n = gb[j];
+        c_n = cb[j];
+      }
+      bool h[4] = {false, false, false, false};
+      if (in) {
+        const float lim = g.w * 1.001f + 1e-6f;
+        const float exl = fmaxf(fmaxf(fu0 - g.x, g.x - ful), 0.0f);
+        const float exr = fmaxf(fmaxf(fur0 - g.x, g.x - fure), 0.0f);
+        const float eyt = fmaxf(fmaxf(fv0 - g.y, g.y - fvt), 0.0f);
+        const float eyb = fmaxf(fmaxf(fvb0 - g.y, g.y - fvbe), 0.0f);
+        const float xl = exl * exl, xr = exr * exr, yt = eyt * eyt, yb = eyb * eyb;
+        h[0] = xl + yt <= lim;
+        h[1] = has_r && xr + yt <= lim;
+        h[2] = has_b && xl + yb <= lim;
+        h[3] = has_r && has_b && xr + yb <= lim;
+      }
+      unsigned long long m[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) m[q] = __ballot(h[q]);
+      if ((m[0] | m[1] | m[2] | m[3]) == 0) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (h[q]) {
+          const int slot = __builtin_amdgcn_mbcnt_hi((unsigned)(m[q] >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((unsigned)m[q], 0));
+          float4* d = lst + (q * kQuarterList + slot) * 2;
+          d[0] = g;
+          d[1] = c;
+        }
+      }
+      int nit[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int n = __popcll(m[q]);
+        const int pad = (-n) & 3;
+        if (lane < pad) {
+          float4* d = lst + (q * kQuarterList + n + lane) * 2;
+          d[0] = null_geo;
+          d[1] = zero4;
+        }
+        nit[q] = (n + 3) >> 2;
+      }
+      wave_lds_sync();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float fu = pu + (float)(4 * (q & 1)), fv = pv + (float)(4 * (q >> 1));
+        const float4* L = lst + (q * kQuarterList + grp) * 2;
+        for (int i = 0; i < nit[q]; ++i) {
+          const float4 r = L[8 * i];
+          const float4 cv = L[8 * i + 1];
+          // radius test exactly as specified: float32, every operation rounded
+          const float dx = fu - r.x;
+          const float dy = fv - r.y;
+          const float d2 = dx * dx + dy * dy;
+          float w = __builtin_amdgcn_exp2f(d2 * r.z);
+          w = (d2 <= r.w) ? w : 0.0f;
+          Z[q] += w;
+          const float cc[4] = {cv.x, cv.y, cv.z, cv.w};
+#pragma unroll
+          for (int k = 0; k < CT; ++k) acc[q][k] = __builtin_fmaf(w, cc[k], acc[q][k]);
+        }
+      }
+      wave_lds_sync();
+    }
+  }
+
+  // lane groups: (g0 + g1) + (g2 + g3) per quarter; lane group q keeps quarter q
+  float part[CT + 1];
+#pragma unroll
+  for (int k = 0; k <= CT; ++k) part[k] = 0.0f;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+#pragma unroll
+    for (int k = 0; k <= CT; ++k) {
+      float a = k < CT ? acc[q][k] : Z[q];
+      a += __shfl_xor(a, 16);
+      a += __shfl_xor(a, 32);
+      part[k] = grp == q ? a : part[k];
+    }
+  }
+  // wavefronts of a block, through the (now free) list memory
+  if constexpr (kFwdSplit > 1) {
+    __syncthreads();
+    float* red = reinterpret_cast<float*>(s_rec);
+#pragma unroll
+    for (int k = 0; k <= CT; ++k) red[(k * 4 + wid) * 64 + lane] = part[k];
+    __syncthreads();
+    const float* r0 = red + (wid - phase) * 64 + lane;
+#pragma unroll
+    for (int k = 0; k <= CT; ++k) {
+      const float* r = r0 + k * 256;
+      part[k] = kFwdSplit == 2 ? r[0] + r[64] : (r[0] + r[64]) + (r[128] + r[192]);
+    }
+  }
+  const float Zo = part[CT];
+  const int u = u0 + 4 * (grp & 1) + (p & 3), vv = v0 + 4 * (grp >> 1) + (p >> 2);
+  if (active && phase == 0 && u <= ue && vv <= ve) {
+    const size_t HW = (size_t)v.H * v.W;
+    const size_t pix = (size_t)vv * v.W + u;
+#pragma unroll
+    for (int k = 0; k < CT; ++k) {
+      if (k < v.C) v.out[k * HW + pix] = Zo > 0.0f ? part[k] / Zo : 0.0f;
+    }
+    v.Z[pix] = Zo;
   }
 }
 

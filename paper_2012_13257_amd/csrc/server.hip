@@ -62,15 +62,14 @@ struct PhaseLds {
                               : (PH == PH_BPOINT)                 ? 256 + 64
                               : (PH >= PH_HIST0 && PH <= PH_HIST2) ? 256
                                                                   : 4;
-  static constexpr int f4 = PH == PH_FWD ? 4 * 64 : 1;
+  static constexpr int f4 = PH == PH_FWD ? dev::fwd_quarter_lds_f4() : 1;
 };
 
 template <int PH>
 __global__ __launch_bounds__(256) void kj_phase(const JobTable* __restrict__ T) {
   __shared__ float red4[4];
   __shared__ int lds_i[PhaseLds<PH>::ints];
-  __shared__ float4 s_geo[PhaseLds<PH>::f4];
-  __shared__ float4 s_col[PhaseLds<PH>::f4];
+  __shared__ float4 s_rec[PhaseLds<PH>::f4];
   const int nj = T->njobs;
   const int* U = T->units[PH];
   const int total = U[nj];
@@ -96,10 +95,10 @@ __global__ __launch_bounds__(256) void kj_phase(const JobTable* __restrict__ T) 
       dev::bin_gather(v, local);
     } else if constexpr (PH == PH_FWD) {
       switch (T->ct[lo]) {
-        case 1: dev::forward_tile<1>(v, local, s_geo, s_col); break;
-        case 2: dev::forward_tile<2>(v, local, s_geo, s_col); break;
-        case 3: dev::forward_tile<3>(v, local, s_geo, s_col); break;
-        default: dev::forward_tile<4>(v, local, s_geo, s_col); break;
+        case 1: dev::forward_block_q<1>(v, local, s_rec); break;
+        case 2: dev::forward_block_q<2>(v, local, s_rec); break;
+        case 3: dev::forward_block_q<3>(v, local, s_rec); break;
+        default: dev::forward_block_q<4>(v, local, s_rec); break;
       }
     } else if constexpr (PH == PH_BPIX) {
       switch (T->ct[lo]) {
@@ -237,7 +236,7 @@ class GpuExecutor {
       }
       u[PH_FINISH] = dev::finish_units(g.N);
       u[PH_GATHER] = g.N > 0 ? g.units256 : 0;
-      u[PH_FWD] = dev::fwd_tiles(g.bx_blocks, g.by_blocks);
+      u[PH_FWD] = dev::fwd_units(g.bx_blocks, g.by_blocks);
       u[PH_BPIX] = bwd ? (g.H * g.W + 255) / 256 : 0;
       u[PH_BPOINT] = bwd && g.N > 0 ? g.units256 : 0;
       u[PH_BSIG] = bwd && !g.per_point && r.grad_sigma ? 1 : 0;

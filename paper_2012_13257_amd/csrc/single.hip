@@ -35,20 +35,24 @@ __global__ __launch_bounds__(256) void k_bin_gather(ImageView v0) {
   dev::bin_gather(image_of(v0, blockIdx.y), blockIdx.x);
 }
 
-// Tiles are taken in row-major order, so consecutive workgroups -- which the
-// dispatcher spreads round-robin over the 8 XCDs -- interleave over the image
-// and every XCD gets a share of the dense and of the sparse regions.  (Giving
-// each XCD a contiguous band of tiles keeps halo reads in one L2 but leaves
-// the XCDs that own dense bands running long after the others: measured
-// slower on clustered point sets.)
+// Work units are taken in row-major order, so consecutive workgroups -- which
+// the dispatcher spreads round-robin over the 8 XCDs -- interleave over the
+// image and every XCD gets a share of the dense and of the sparse regions.
+// Up to 4 channels: one unit = one 8x8 block (its candidates split over the
+// four wavefronts); more channels: one unit = one 16x16 tile, a wavefront per
+// 8x8 block.
 template <int CT>
-__global__ __launch_bounds__(256) void k_forward(ImageView v0, int tiles_per_image) {
-  constexpr int CS = CT < 4 ? 4 : CT;
-  __shared__ float4 s_geo[4 * 64];
-  __shared__ float4 s_col[4 * 64 * (CS / 4)];
+__global__ __launch_bounds__(256) void k_forward(ImageView v0, int units_per_image) {
   const int t = blockIdx.x;
-  const int b = t / tiles_per_image;
-  dev::forward_tile<CT>(image_of(v0, b), t - b * tiles_per_image, s_geo, s_col);
+  const int b = t / units_per_image;
+  if constexpr (CT <= 4) {
+    __shared__ float4 s_rec[dev::fwd_quarter_lds_f4()];
+    dev::forward_block_q<CT>(image_of(v0, b), t - b * units_per_image, s_rec);
+  } else {
+    __shared__ float4 s_geo[4 * 64];
+    __shared__ float4 s_col[4 * 64 * (CT / 4)];
+    dev::forward_tile<CT>(image_of(v0, b), t - b * units_per_image, s_geo, s_col);
+  }
 }
 
 template <int CT>
@@ -78,7 +82,8 @@ inline unsigned cdiv(long long n, int d) { return (unsigned)((n + d - 1) / d); }
 
 template <int CT>
 hipError_t launch_forward_t(const Geometry& g, const ImageView& v0, hipStream_t st) {
-  const int per = dev::fwd_tiles(g.bx_blocks, g.by_blocks);
+  const int per = CT <= 4 ? dev::fwd_units(g.bx_blocks, g.by_blocks)
+                          : dev::fwd_tiles(g.bx_blocks, g.by_blocks);
   const long long total = (long long)per * g.B;
   if (total >= (1LL << 31)) return hipErrorInvalidValue;
   ProfRange pr_("forward", st);
