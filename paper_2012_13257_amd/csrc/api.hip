@@ -127,7 +127,8 @@ int interp_forward(const interp_problem* prob, const float* pos, const float* si
   hipStream_t st = static_cast<hipStream_t>(stream);
   const ImageView v0 = make_view(g, L, saved, workspace, pos, sigma, values, out, nullptr, nullptr,
                                  nullptr, nullptr);
-  hipError_t e = launch_forward_all(g, v0, st);
+  int* fplan = reinterpret_cast<int*>(static_cast<char*>(workspace) + L.fplan);
+  hipError_t e = launch_forward_all(g, v0, fplan, st);
   if (e != hipSuccess) return fail_hip(e, "forward kernels");
   g_last_error.clear();
   return INTERP_OK;

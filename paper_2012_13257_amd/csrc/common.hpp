@@ -45,6 +45,34 @@ inline void radix_plan(int nb, int* npass, int* dbits, int* kbits) {
   *dbits = *npass ? (bits + *npass - 1) / *npass : 0;
 }
 
+// Forward work units (see forward_block_q): a unit is one 256-thread block
+// covering kUBW x kUBH blocks of 8x8 pixels, each evaluated by kFwdSplit
+// wavefronts.  The dispatcher hands consecutive workgroups to the 8 XCDs in
+// turn, so when units are launched in number order (the serving path) unit i
+// runs on XCD i % 8: units are numbered in groups of 8 that tile a 4 x 2
+// patch of units, and each XCD gets the same position in every patch -- a
+// regular lattice over the image, so a dense region is shared by all XCDs
+// instead of loading the few that own its columns.  (The single-call path
+// launches them in the order of a cost plan instead, heaviest first.)
+constexpr int kFwdSplit = 2;
+constexpr int kUBW = kFwdSplit == 1 ? 2 : kFwdSplit == 2 ? 2 : 1;
+constexpr int kUBH = kFwdSplit == 1 ? 2 : 1;
+constexpr int kPlanBuckets = 32;  // cost classes of the forward's work order
+struct FwdUnits {
+  int ux, uy, stx;  // units per row / column, 4x2 patches per row
+  __host__ __device__ FwdUnits(int bx_blocks, int by_blocks)
+      : ux((bx_blocks + kUBW - 1) / kUBW), uy((by_blocks + kUBH - 1) / kUBH), stx((ux + 3) / 4) {}
+  __host__ __device__ int count() const { return stx * ((uy + 1) / 2) * 8; }
+  // unit number -> unit coordinates; false for the padding units of the patches
+  __host__ __device__ bool coords(int unit, int* cx, int* cy) const {
+    const int st = unit >> 3, x = unit & 7;
+    const int sy = st / stx;
+    *cx = 4 * (st - sy * stx) + (x & 3);
+    *cy = 2 * sy + (x >> 2);
+    return *cx < ux && *cy < uy;
+  }
+};
+
 struct Geometry {
   int B, N, C, H, W, T;
   int nbx, nby, nb;
@@ -55,6 +83,7 @@ struct Geometry {
   int npass, dbits, kbits;             // radix sort of the bin keys
   int ntiles;                          // radix tiles per image
   int units256;                        // ceil(N / 256)
+  int fwd_units;                       // forward work units per image (up to 4 channels)
 };
 
 // Byte offsets of every array inside the saved buffer and the workspace.
@@ -62,7 +91,7 @@ struct Layout {
   // saved
   size_t Z, reach, offset, perm, geo, col, saved_bytes;
   // workspace
-  size_t binof, keysF, kA, vA, kB, vB, hist, dtot, rpart, trec, prec, gpart, work_bytes;
+  size_t binof, keysF, kA, vA, kB, vB, hist, dtot, rpart, trec, prec, gpart, fplan, work_bytes;
 };
 
 inline Layout make_layout(const Geometry& g) {
@@ -89,6 +118,9 @@ inline Layout make_layout(const Geometry& g) {
   L.trec = o;   o = align_up(o + B * N * (4 + size_t(g.CS)) * 4);
   L.prec = o;   o = align_up(o + B * HW * size_t(g.CP) * 4);
   L.gpart = o;  o = align_up(o + B * size_t(g.units256) * 4 + 4);
+  // forward work order: 64 counters (bucket sizes, work cursor), then
+  // kPlanBuckets lists of up to B * fwd_units unit numbers
+  L.fplan = o;  o = align_up(o + (64 + size_t(kPlanBuckets) * B * g.fwd_units) * 4);
   L.work_bytes = o;
   return L;
 }
@@ -124,6 +156,8 @@ inline std::string make_geometry(const interp_problem* p, Geometry* g) {
   radix_plan(g->nb, &g->npass, &g->dbits, &g->kbits);
   g->ntiles = (p->N + kRadixTile - 1) / kRadixTile;
   g->units256 = (p->N + 255) / 256;
+  g->fwd_units = FwdUnits(g->bx_blocks, g->by_blocks).count();
+  if ((long long)g->fwd_units * g->B * kPlanBuckets >= (1LL << 31)) return "image too large";
   return "";
 }
 
@@ -254,7 +288,7 @@ struct ProfRange {
 };
 
 // Host launchers of the single-call path (single.hip).
-hipError_t launch_forward_all(const Geometry& g, const ImageView& v0, hipStream_t st);
+hipError_t launch_forward_all(const Geometry& g, const ImageView& v0, int* fplan, hipStream_t st);
 hipError_t launch_backward_all(const Geometry& g, const ImageView& v0, hipStream_t st);
 hipError_t launch_debug_count(const Geometry& g, const ImageView& v0, int* count, hipStream_t st);
 

@@ -15,9 +15,11 @@
 //                  counting-sort order by bin, ties by point index
 //   bin_finish     bin offsets from the sorted keys; per-image reach
 //   bin_gather     sorted point records (x, y, k, R2) and values
+//   fwd_plan       (single-call path) cost class of every forward unit, for
+//                  a heaviest-first launch order
 //   forward        the gather: per 8x8 pixel block, candidates from the bins
 //                  within reach, culled per 4x4 quarter of the block, hits
-//                  evaluated per pixel (units numbered XCD-aware)
+//                  evaluated per pixel
 // Backward (quotient rule on Eq. 1; formulas in include/gmminterp.h):
 //   bwd_pixel      G'_ik = G_ik / Z_i and beta_i per pixel
 //   bwd_point      per point: walk its disk's bounding box, recompute w_ij,
@@ -432,35 +434,49 @@ __device__ inline void forward_tile(const ImageView& v, int tile, float4* s_geo 
 // combined in a fixed order: the lane groups of a quarter as (g0 + g1) +
 // (g2 + g3), then the wavefronts of a block likewise.
 constexpr int kQuarterList = 68;  // 64 hits + up to 3 padding entries
-constexpr int kFwdSplit = 2;      // wavefronts per 8x8 block
 __host__ __device__ inline constexpr int fwd_quarter_lds_f4() {
   return 4 * 4 * kQuarterList * 2;  // waves x quarters x entries x (geo, values)
 }
 
-// Forward work units.  A unit (one 256-thread block) covers UBW x UBH blocks
-// of 8x8 pixels.  The dispatcher hands consecutive workgroups to the 8 XCDs
-// in turn, so unit number i runs on XCD i % 8: units are numbered in groups
-// of 8 that tile a 4 x 2 patch of units, and each XCD gets the same position
-// in every patch -- a regular lattice over the image, so a dense region is
-// shared by all XCDs instead of loading the few that own its columns.
-constexpr int kUBW = kFwdSplit == 1 ? 2 : kFwdSplit == 2 ? 2 : 1;
-constexpr int kUBH = kFwdSplit == 1 ? 2 : 1;
-struct FwdUnits {
-  int ux, uy, stx;  // units per row / column, 4x2 patches per row
-  __host__ __device__ FwdUnits(int bx_blocks, int by_blocks)
-      : ux((bx_blocks + kUBW - 1) / kUBW), uy((by_blocks + kUBH - 1) / kUBH), stx((ux + 3) / 4) {}
-  __host__ __device__ int count() const { return stx * ((uy + 1) / 2) * 8; }
-  // unit number -> unit coordinates; false for the padding units of the patches
-  __host__ __device__ bool coords(int unit, int* cx, int* cy) const {
-    const int st = unit >> 3, x = unit & 7;
-    const int sy = st / stx;
-    *cx = 4 * (st - sy * stx) + (x & 3);
-    *cy = 2 * sy + (x >> 2);
-    return *cx < ux && *cy < uy;
-  }
-};
 __host__ __device__ inline int fwd_units(int bx_blocks, int by_blocks) {
   return FwdUnits(bx_blocks, by_blocks).count();
+}
+
+// Bins whose records can reach pixels of the box [u0, ue] x [v0, ve]: the
+// bin columns [*bx_lo, *bx_hi] of the bin rows [*by_lo, *by_hi].
+__device__ inline void box_bins(const ImageView& v, int u0, int ue, int v0, int ve, int* bx_lo,
+                                int* bx_hi, int* by_lo, int* by_hi) {
+  const float Rh = conservative_reach(v.reach[0]);
+  *bx_lo = bin_coord((float)u0 - Rh, v.inv_tile, v.nbx);
+  *bx_hi = bin_coord((float)ue + Rh, v.inv_tile, v.nbx);
+  *by_lo = bin_coord((float)v0 - Rh, v.inv_tile, v.nby);
+  *by_hi = bin_coord((float)ve + Rh, v.inv_tile, v.nby);
+}
+
+// Pixel box of block (bxb, byb): [u0, ue] x [v0, ve]
+__device__ inline void block_box(const ImageView& v, int bxb, int byb, int* u0, int* ue, int* v0,
+                                 int* ve) {
+  *u0 = bxb * kBlockSide;
+  *v0 = byb * kBlockSide;
+  *ue = min(*u0 + kBlockSide - 1, v.W - 1);
+  *ve = min(*v0 + kBlockSide - 1, v.H - 1);
+}
+
+// Candidate records of the blocks of a forward unit (its cost estimate).
+__device__ inline int unit_candidates(const ImageView& v, int unit) {
+  int ucx, ucy;
+  if (!FwdUnits(v.bx_blocks, v.by_blocks).coords(unit, &ucx, &ucy)) return 0;
+  int n = 0;
+  for (int sb = 0; sb < 4 / kFwdSplit; ++sb) {
+    const int bxb = ucx * kUBW + sb % kUBW, byb = ucy * kUBH + sb / kUBW;
+    if (bxb >= v.bx_blocks || byb >= v.by_blocks) continue;
+    int u0, ue, v0, ve, bx_lo, bx_hi, by_lo, by_hi;
+    block_box(v, bxb, byb, &u0, &ue, &v0, &ve);
+    box_bins(v, u0, ue, v0, ve, &bx_lo, &bx_hi, &by_lo, &by_hi);
+    for (int r = by_lo; r <= by_hi; ++r)
+      n += v.offset[r * v.nbx + bx_hi + 1] - v.offset[r * v.nbx + bx_lo];
+  }
+  return n;
 }
 
 template <int CT>
@@ -474,10 +490,8 @@ __device__ inline void forward_block_q(const ImageView& v, int unit, float4* s_r
   const bool in_grid = FwdUnits(v.bx_blocks, v.by_blocks).coords(unit, &ucx, &ucy);
   const int bxb = ucx * kUBW + sb % kUBW, byb = ucy * kUBH + sb / kUBW;
   const bool active = in_grid && bxb < v.bx_blocks && byb < v.by_blocks;
-  const int u0 = (active ? bxb : 0) * kBlockSide;
-  const int v0 = (active ? byb : 0) * kBlockSide;
-  const int ue = min(u0 + kBlockSide - 1, v.W - 1);
-  const int ve = min(v0 + kBlockSide - 1, v.H - 1);
+  int u0, ue, v0, ve;
+  block_box(v, active ? bxb : 0, active ? byb : 0, &u0, &ue, &v0, &ve);
 
   // quarter boxes: columns [u0, ul] and [u0 + 4, ur], rows [v0, vt] and [v0 + 4, vb]
   const float fu0 = (float)u0, fv0 = (float)v0;
@@ -487,12 +501,12 @@ __device__ inline void forward_block_q(const ImageView& v, int unit, float4* s_r
   // this lane's pixel in quarter q: (u0 + 4 (q & 1) + p % 4, v0 + 4 (q >> 1) + p / 4)
   const float pu = fu0 + (float)(p & 3), pv = fv0 + (float)(p >> 2);
 
-  const float Rh = conservative_reach(v.reach[0]);
-  const int bx_lo = __builtin_amdgcn_readfirstlane(bin_coord(fu0 - Rh, v.inv_tile, v.nbx));
-  const int bx_hi = __builtin_amdgcn_readfirstlane(bin_coord((float)ue + Rh, v.inv_tile, v.nbx));
-  const int by_lo = __builtin_amdgcn_readfirstlane(bin_coord(fv0 - Rh, v.inv_tile, v.nby));
-  const int by_hi = active ? __builtin_amdgcn_readfirstlane(bin_coord((float)ve + Rh, v.inv_tile, v.nby))
-                           : by_lo - 1;
+  int bb[4];
+  box_bins(v, u0, ue, v0, ve, &bb[0], &bb[1], &bb[2], &bb[3]);
+  const int bx_lo = __builtin_amdgcn_readfirstlane(bb[0]);
+  const int bx_hi = __builtin_amdgcn_readfirstlane(bb[1]);
+  const int by_lo = __builtin_amdgcn_readfirstlane(bb[2]);
+  const int by_hi = active ? __builtin_amdgcn_readfirstlane(bb[3]) : by_lo - 1;
   const float4* gb = v.geo;
   const float4* cb = reinterpret_cast<const float4*>(v.col);
 
@@ -524,56 +538,62 @@ __device__ inline void forward_block_q(const ImageView& v, int unit, float4* s_r
       if (lane >= o) incl += y;
     }
     const int total = __builtin_amdgcn_readlane(incl, 63);
-    // record index of position t of the concatenation (t < total): the row r
-    // with excl_r <= t < incl_r, index s_r + t - excl_r
-    auto record_of = [&](int t) {
-      int base = 0;
-      for (int r = 0; r < nr; ++r) {
-        const int ex = __builtin_amdgcn_readlane(incl - len, r);
-        const int sb = __builtin_amdgcn_readlane(s_r, r);
-        base = t >= ex ? sb - ex : base;
+    // Record index of position t of the concatenation: s_r + t - excl_r for
+    // the row r with excl_r <= t < incl_r.  Positions are visited in
+    // increasing order, so a wave-uniform row cursor `rc` (the row holding the
+    // first position of the current chunk) only moves forward.
+    const int ex_l = incl - len, base_l = s_r - ex_l;
+    int rc = 0;
+    auto chunk_records = [&](int c) {
+      while (__builtin_amdgcn_readlane(incl, rc) <= c) ++rc;
+      const int t = c + lane;
+      int j = __builtin_amdgcn_readlane(base_l, rc) + t;
+      for (int r = rc + 1; r < nr; ++r) {
+        const int ex = __builtin_amdgcn_readlane(ex_l, r);
+        if (ex >= c + 64) break;
+        j = t >= ex ? __builtin_amdgcn_readlane(base_l, r) + t : j;
       }
-      return base + t;
+      return j;
     };
 
     int c0 = phase * 64;
     float4 g_n = zero4, c_n = zero4;
-    if (c0 + lane < total) {
-      const int j = record_of(c0 + lane);
-      g_n = gb[j];
-      c_n = cb[j];
+    if (c0 < total) {
+      const int j = chunk_records(c0);
+      if (c0 + lane < total) {
+        g_n = gb[j];
+        c_n = cb[j];
+      }
     }
     for (; c0 < total; c0 += 64 * kFwdSplit) {
       const bool in = c0 + lane < total;
       const float4 g = g_n, c = c_n;
       const int cn = c0 + 64 * kFwdSplit;
-      if (cn + lane < total) {
-        const int j = record_of(cn + lane);
-        g_n = gb[j];
-        c_n = cb[j];
+      if (cn < total) {
+        const int j = chunk_records(cn);
+        if (cn + lane < total) {
+          g_n = gb[j];
+          c_n = cb[j];
+        }
       }
-      bool h[4] = {false, false, false, false};
-      if (in) {
-        const float lim = g.w * 1.001f + 1e-6f;
-        const float exl = fmaxf(fmaxf(fu0 - g.x, g.x - ful), 0.0f);
-        const float exr = fmaxf(fmaxf(fur0 - g.x, g.x - fure), 0.0f);
-        const float eyt = fmaxf(fmaxf(fv0 - g.y, g.y - fvt), 0.0f);
-        const float eyb = fmaxf(fmaxf(fvb0 - g.y, g.y - fvbe), 0.0f);
-        const float xl = exl * exl, xr = exr * exr, yt = eyt * eyt, yb = eyb * eyb;
-        h[0] = xl + yt <= lim;
-        h[1] = has_r && xr + yt <= lim;
-        h[2] = has_b && xl + yb <= lim;
-        h[3] = has_r && has_b && xr + yb <= lim;
-      }
+      // disk of the candidate against the box of each quarter (conservative)
+      const float lim = g.w * 1.001f + 1e-6f;
+      const float exl = fmaxf(fmaxf(fu0 - g.x, g.x - ful), 0.0f);
+      const float exr = fmaxf(fmaxf(fur0 - g.x, g.x - fure), 0.0f);
+      const float eyt = fmaxf(fmaxf(fv0 - g.y, g.y - fvt), 0.0f);
+      const float eyb = fmaxf(fmaxf(fvb0 - g.y, g.y - fvbe), 0.0f);
+      const float xl = exl * exl, xr = exr * exr, yt = eyt * eyt, yb = eyb * eyb;
+      const bool h[4] = {in && xl + yt <= lim, in && has_r && xr + yt <= lim,
+                         in && has_b && xl + yb <= lim, in && has_r && has_b && xr + yb <= lim};
       unsigned long long m[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) m[q] = __ballot(h[q]);
       if ((m[0] | m[1] | m[2] | m[3]) == 0) continue;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
+        const int slot = __builtin_amdgcn_mbcnt_hi((unsigned)(m[q] >> 32),
+                                                   __builtin_amdgcn_mbcnt_lo((unsigned)m[q], 0));
         if (h[q]) {
-          const int slot = __builtin_amdgcn_mbcnt_hi((unsigned)(m[q] >> 32),
-                                                     __builtin_amdgcn_mbcnt_lo((unsigned)m[q], 0));
           float4* d = lst + (q * kQuarterList + slot) * 2;
           d[0] = g;
           d[1] = c;

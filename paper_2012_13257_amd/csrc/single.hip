@@ -26,33 +26,77 @@ __global__ __launch_bounds__(256) void k_radix_scatter(ImageView v0, int p) {
   dev::radix_scatter(image_of(v0, blockIdx.y), p, blockIdx.x, lds);
 }
 
-__global__ __launch_bounds__(256) void k_bin_finish(ImageView v0) {
+// also clears the counters of the forward's work order (fplan, 64 ints)
+__global__ __launch_bounds__(256) void k_bin_finish(ImageView v0, int* fplan) {
   __shared__ float red4[4];
+  if (fplan && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 64) fplan[threadIdx.x] = 0;
   dev::bin_finish(image_of(v0, blockIdx.y), blockIdx.x, red4);
+}
+
+// Work order of the forward, heaviest units first: unit number id = image *
+// units + unit goes to the list of its cost class (floor(log2) + 1 of its
+// candidate count, 0 for none).  fplan[0..31]: list sizes, lists from
+// fplan + 64 (kPlanBuckets x total).  A
+// workgroup ranks its units per class in LDS and reserves each class's slots
+// with one global atomic.  The order inside a list follows the atomics and
+// varies from run to run; the results do not depend on it (each unit computes
+// its pixels on its own).
+__global__ __launch_bounds__(256) void k_fwd_plan(ImageView v0, int units, int total, int* fplan) {
+  __shared__ int cnt[kPlanBuckets], base[kPlanBuckets];
+  const int id = blockIdx.x * 256 + threadIdx.x;
+  if (threadIdx.x < kPlanBuckets) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  int cls = -1, rank = 0;
+  if (id < total) {
+    const int b = id / units;
+    const int cost = dev::unit_candidates(image_of(v0, b), id - b * units);
+    cls = cost == 0 ? 0 : min(kPlanBuckets - 1, 32 - __clz(cost));
+    rank = atomicAdd(&cnt[cls], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < kPlanBuckets && cnt[threadIdx.x] > 0)
+    base[threadIdx.x] = atomicAdd(&fplan[threadIdx.x], cnt[threadIdx.x]);
+  __syncthreads();
+  if (cls >= 0) fplan[64 + (size_t)cls * total + base[cls] + rank] = id;
 }
 
 __global__ __launch_bounds__(256) void k_bin_gather(ImageView v0) {
   dev::bin_gather(image_of(v0, blockIdx.y), blockIdx.x);
 }
 
-// Work units are taken in row-major order, so consecutive workgroups -- which
-// the dispatcher spreads round-robin over the 8 XCDs -- interleave over the
-// image and every XCD gets a share of the dense and of the sparse regions.
-// Up to 4 channels: one unit = one 8x8 block (its candidates split over the
-// four wavefronts); more channels: one unit = one 16x16 tile, a wavefront per
-// 8x8 block.
+// Forward gather.  Up to 4 channels: workgroup i takes the i-th unit of the
+// plan's work order, so the dispatcher starts the heaviest units first and
+// fills in the light ones as compute units free up (a unit's result does not
+// depend on which workgroup computes it or when).  More channels: one
+// workgroup per 16x16 tile, a wavefront per 8x8 block.
 template <int CT>
-__global__ __launch_bounds__(256) void k_forward(ImageView v0, int units_per_image) {
-  const int t = blockIdx.x;
-  const int b = t / units_per_image;
-  if constexpr (CT <= 4) {
-    __shared__ float4 s_rec[dev::fwd_quarter_lds_f4()];
-    dev::forward_block_q<CT>(image_of(v0, b), t - b * units_per_image, s_rec);
-  } else {
-    __shared__ float4 s_geo[4 * 64];
-    __shared__ float4 s_col[4 * 64 * (CT / 4)];
-    dev::forward_tile<CT>(image_of(v0, b), t - b * units_per_image, s_geo, s_col);
+__global__ __launch_bounds__(256) void k_forward_lpt(ImageView v0, int units, int total,
+                                                     const int* fplan) {
+  __shared__ float4 s_rec[dev::fwd_quarter_lds_f4()];
+  const int lane = threadIdx.x & 63;
+  // lane l < 32: work items in the classes 31 .. 31 - l (heaviest first)
+  int incl = lane < kPlanBuckets ? fplan[kPlanBuckets - 1 - lane] : 0;
+#pragma unroll
+  for (int o = 1; o < 32; o <<= 1) {
+    const int y = __shfl_up(incl, o);
+    if (lane >= o) incl += y;
   }
+  const int w = blockIdx.x;
+  const unsigned long long m = __ballot(lane < kPlanBuckets && w < incl);
+  const int k = __ffsll((long long)m) - 1;  // the class list holding item w
+  const int before = k > 0 ? __shfl(incl, k - 1) : 0;
+  const int id = fplan[64 + (size_t)(kPlanBuckets - 1 - k) * total + (w - before)];
+  const int b = id / units;
+  dev::forward_block_q<CT>(image_of(v0, b), id - b * units, s_rec);
+}
+
+template <int CT>
+__global__ __launch_bounds__(256) void k_forward(ImageView v0, int tiles_per_image) {
+  __shared__ float4 s_geo[4 * 64];
+  __shared__ float4 s_col[4 * 64 * (CT / 4)];
+  const int t = blockIdx.x;
+  const int b = t / tiles_per_image;
+  dev::forward_tile<CT>(image_of(v0, b), t - b * tiles_per_image, s_geo, s_col);
 }
 
 template <int CT>
@@ -81,13 +125,24 @@ __global__ __launch_bounds__(256) void k_debug_count(ImageView v0, int* count) {
 inline unsigned cdiv(long long n, int d) { return (unsigned)((n + d - 1) / d); }
 
 template <int CT>
-hipError_t launch_forward_t(const Geometry& g, const ImageView& v0, hipStream_t st) {
-  const int per = CT <= 4 ? dev::fwd_units(g.bx_blocks, g.by_blocks)
-                          : dev::fwd_tiles(g.bx_blocks, g.by_blocks);
-  const long long total = (long long)per * g.B;
-  if (total >= (1LL << 31)) return hipErrorInvalidValue;
-  ProfRange pr_("forward", st);
-  hipLaunchKernelGGL(k_forward<CT>, dim3((unsigned)total), dim3(256), 0, st, v0, per);
+hipError_t launch_forward_t(const Geometry& g, const ImageView& v0, int* fplan, hipStream_t st) {
+  if constexpr (CT <= 4) {
+    const int total = g.fwd_units * g.B;  // checked against 2^31 / kPlanBuckets
+    {
+      ProfRange pr_("fwd_plan", st);
+      hipLaunchKernelGGL(k_fwd_plan, dim3(cdiv(total, 256)), dim3(256), 0, st, v0, g.fwd_units,
+                         total, fplan);
+    }
+    ProfRange pr_("forward", st);
+    hipLaunchKernelGGL(k_forward_lpt<CT>, dim3((unsigned)total), dim3(256), 0, st, v0,
+                       g.fwd_units, total, fplan);
+  } else {
+    const int per = dev::fwd_tiles(g.bx_blocks, g.by_blocks);
+    const long long total = (long long)per * g.B;
+    if (total >= (1LL << 31)) return hipErrorInvalidValue;
+    ProfRange pr_("forward", st);
+    hipLaunchKernelGGL(k_forward<CT>, dim3((unsigned)total), dim3(256), 0, st, v0, per);
+  }
   return hipSuccess;
 }
 
@@ -111,7 +166,7 @@ hipError_t launch_backward_t(const Geometry& g, const ImageView& v0, hipStream_t
 
 }  // namespace
 
-hipError_t launch_forward_all(const Geometry& g, const ImageView& v0, hipStream_t st) {
+hipError_t launch_forward_all(const Geometry& g, const ImageView& v0, int* fplan, hipStream_t st) {
   if (g.N > 0) {
     ProfRange pr_("bin_keys", st);
     hipLaunchKernelGGL(k_bin_keys, dim3(g.units256, g.B), dim3(256), 0, st, v0);
@@ -133,7 +188,8 @@ hipError_t launch_forward_all(const Geometry& g, const ImageView& v0, hipStream_
   }
   {
     ProfRange pr_("bin_finish", st);
-    hipLaunchKernelGGL(k_bin_finish, dim3(dev::finish_units(g.N), g.B), dim3(256), 0, st, v0);
+    hipLaunchKernelGGL(k_bin_finish, dim3(dev::finish_units(g.N), g.B), dim3(256), 0, st, v0,
+                       fplan);
   }
   if (g.N > 0) {
     ProfRange pr_("bin_gather", st);
@@ -142,13 +198,13 @@ hipError_t launch_forward_all(const Geometry& g, const ImageView& v0, hipStream_
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   switch (g.CT) {
-    case 1: e = launch_forward_t<1>(g, v0, st); break;
-    case 2: e = launch_forward_t<2>(g, v0, st); break;
-    case 3: e = launch_forward_t<3>(g, v0, st); break;
-    case 4: e = launch_forward_t<4>(g, v0, st); break;
-    case 8: e = launch_forward_t<8>(g, v0, st); break;
-    case 16: e = launch_forward_t<16>(g, v0, st); break;
-    case 32: e = launch_forward_t<32>(g, v0, st); break;
+    case 1: e = launch_forward_t<1>(g, v0, fplan, st); break;
+    case 2: e = launch_forward_t<2>(g, v0, fplan, st); break;
+    case 3: e = launch_forward_t<3>(g, v0, fplan, st); break;
+    case 4: e = launch_forward_t<4>(g, v0, fplan, st); break;
+    case 8: e = launch_forward_t<8>(g, v0, fplan, st); break;
+    case 16: e = launch_forward_t<16>(g, v0, fplan, st); break;
+    case 32: e = launch_forward_t<32>(g, v0, fplan, st); break;
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;
