@@ -60,7 +60,7 @@ template <int PH>
 struct PhaseLds {
   static constexpr int ints = (PH >= PH_SCAT0 && PH <= PH_SCAT2) ? dev::radix_scatter_lds_ints()
                               : (PH == PH_BPOINT)                 ? 256 + 64
-                              : (PH >= PH_HIST0 && PH <= PH_HIST2) ? 256
+                              : (PH >= PH_HIST0 && PH <= PH_HIST2) || PH == PH_KEYS ? 256
                                                                   : 4;
   static constexpr int f4 = PH == PH_FWD ? dev::fwd_quarter_lds_f4() : 1;
 };
@@ -82,11 +82,11 @@ __global__ __launch_bounds__(256) void kj_phase(const JobTable* __restrict__ T) 
     const int local = u - U[lo];
     const ImageView& v = T->view[lo];
     if constexpr (PH == PH_KEYS) {
-      dev::bin_keys(v, local, red4);
+      dev::bin_keys(v, local, red4, lds_i);
     } else if constexpr (PH >= PH_HIST0 && PH <= PH_HIST2) {
       dev::radix_hist(v, PH - PH_HIST0, local, lds_i);
     } else if constexpr (PH >= PH_SCAN0 && PH <= PH_SCAN2) {
-      dev::radix_scan_rows(v, PH - PH_SCAN0, local);
+      dev::radix_scan_digit(v, PH - PH_SCAN0, local, lds_i);
     } else if constexpr (PH >= PH_SCAT0 && PH <= PH_SCAT2) {
       dev::radix_scatter(v, PH - PH_SCAT0, local, lds_i);
     } else if constexpr (PH == PH_FINISH) {
@@ -165,7 +165,6 @@ class GpuExecutor {
       if ((e = hipStreamBeginCapture(x.stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
         return fail_hip(e, "hipStreamBeginCapture");
       enqueue_phase<PH_KEYS>(x.dtab, x.stream);
-      enqueue_phase<PH_HIST0>(x.dtab, x.stream);
       enqueue_phase<PH_SCAN0>(x.dtab, x.stream);
       enqueue_phase<PH_SCAT0>(x.dtab, x.stream);
       enqueue_phase<PH_HIST1>(x.dtab, x.stream);
@@ -226,12 +225,12 @@ class GpuExecutor {
       T->ct[i] = g.CT;
       const bool bwd = r.grad_out != nullptr;
       int u[PH_COUNT] = {};
-      u[PH_KEYS] = g.N > 0 ? g.units256 : 0;
+      u[PH_KEYS] = g.N > 0 ? g.ntiles : 0;
       for (int p = 0; p < kServePasses; ++p) {
         const bool on = p < g.npass && g.N > 0;
         const int width = on ? std::min(g.dbits, g.kbits - p * g.dbits) : 0;
-        u[PH_HIST0 + p] = on ? g.ntiles : 0;
-        u[PH_SCAN0 + p] = on ? ((1 << width) + 3) / 4 : 0;
+        u[PH_HIST0 + p] = on && p > 0 ? g.ntiles : 0;  // bin_keys counts the first pass
+        u[PH_SCAN0 + p] = on ? 1 << width : 0;
         u[PH_SCAT0 + p] = on ? g.ntiles : 0;
       }
       u[PH_FINISH] = dev::finish_units(g.N);

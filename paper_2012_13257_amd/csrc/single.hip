@@ -9,7 +9,8 @@ namespace {
 
 __global__ __launch_bounds__(256) void k_bin_keys(ImageView v0) {
   __shared__ float red4[4];
-  dev::bin_keys(image_of(v0, blockIdx.y), blockIdx.x, red4);
+  __shared__ int lh[256];
+  dev::bin_keys(image_of(v0, blockIdx.y), blockIdx.x, red4, lh);
 }
 
 __global__ __launch_bounds__(256) void k_radix_hist(ImageView v0, int p) {
@@ -18,7 +19,8 @@ __global__ __launch_bounds__(256) void k_radix_hist(ImageView v0, int p) {
 }
 
 __global__ __launch_bounds__(256) void k_radix_scan(ImageView v0, int p) {
-  dev::radix_scan_rows(image_of(v0, blockIdx.y), p, blockIdx.x);
+  __shared__ int tmp4[4];
+  dev::radix_scan_digit(image_of(v0, blockIdx.y), p, blockIdx.x, tmp4);
 }
 
 __global__ __launch_bounds__(256) void k_radix_scatter(ImageView v0, int p) {
@@ -169,17 +171,17 @@ hipError_t launch_backward_t(const Geometry& g, const ImageView& v0, hipStream_t
 hipError_t launch_forward_all(const Geometry& g, const ImageView& v0, int* fplan, hipStream_t st) {
   if (g.N > 0) {
     ProfRange pr_("bin_keys", st);
-    hipLaunchKernelGGL(k_bin_keys, dim3(g.units256, g.B), dim3(256), 0, st, v0);
+    hipLaunchKernelGGL(k_bin_keys, dim3(g.ntiles, g.B), dim3(256), 0, st, v0);
   }
   for (int p = 0; p < g.npass && g.N > 0; ++p) {
-    {
+    if (p > 0) {
       ProfRange pr_("radix_hist", st);
       hipLaunchKernelGGL(k_radix_hist, dim3(g.ntiles, g.B), dim3(256), 0, st, v0, p);
     }
     {
       ProfRange pr_("radix_scan", st);
       const int width = std::min(g.dbits, g.kbits - p * g.dbits);
-      hipLaunchKernelGGL(k_radix_scan, dim3(cdiv(1 << width, 4), g.B), dim3(256), 0, st, v0, p);
+      hipLaunchKernelGGL(k_radix_scan, dim3(1u << width, g.B), dim3(256), 0, st, v0, p);
     }
     {
       ProfRange pr_("radix_scatter", st);
