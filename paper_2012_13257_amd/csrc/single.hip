@@ -106,11 +106,17 @@ __global__ __launch_bounds__(256) void k_bwd_pixel(ImageView v0) {
   dev::bwd_pixel<CT>(image_of(v0, blockIdx.y), blockIdx.x);
 }
 
+// The dispatcher hands workgroup i to XCD i % 8; units of 256 sorted points
+// are assigned so that each XCD walks one contiguous eighth of the sorted
+// order -- a band of the image whose pixel records stay in that XCD's L2 --
+// instead of every XCD touching the whole image.  per8 = ceil(units / 8).
 template <int CT>
-__global__ __launch_bounds__(256) void k_bwd_point(ImageView v0) {
+__global__ __launch_bounds__(256) void k_bwd_point(ImageView v0, int per8) {
   __shared__ float red4[4];
   __shared__ int lds[256 + 64];
-  dev::bwd_point<CT>(image_of(v0, blockIdx.y), blockIdx.x, red4, lds);
+  const int unit = (blockIdx.x & 7) * per8 + (blockIdx.x >> 3);
+  if ((int)(blockIdx.x >> 3) >= per8 || unit >= v0.units256) return;
+  dev::bwd_point<CT>(image_of(v0, blockIdx.y), unit, red4, lds);
 }
 
 __global__ __launch_bounds__(256) void k_bwd_sigma_sum(ImageView v0) {
@@ -157,7 +163,8 @@ hipError_t launch_backward_t(const Geometry& g, const ImageView& v0, hipStream_t
   }
   if (g.N > 0) {
     ProfRange pr_("bwd_point", st);
-    hipLaunchKernelGGL(k_bwd_point<CT>, dim3(g.units256, g.B), dim3(256), 0, st, v0);
+    const int per8 = (g.units256 + 7) / 8;
+    hipLaunchKernelGGL(k_bwd_point<CT>, dim3(8 * per8, g.B), dim3(256), 0, st, v0, per8);
   }
   if (!g.per_point && v0.grad_sigma) {
     ProfRange pr_("bwd_sigma_sum", st);
