@@ -17,7 +17,7 @@ constexpr int kBlockSide = 8;          // one wavefront owns an 8x8 pixel block
 constexpr int kMaxChannels = 32;
 constexpr float kMaxRadius = 12.0f;    // keeps exp2(-r^2/2 * log2(e)) a normal float
 constexpr size_t kAlign = 256;
-constexpr int kRadixItems = 8;         // keys per thread in a radix pass
+constexpr int kRadixItems = 4;         // keys per thread in a radix pass
 constexpr int kRadixTile = 256 * kRadixItems;  // keys per workgroup in a radix pass
 constexpr int kRadixMaxPasses = 4;     // bin keys of up to 32 bits
 
@@ -91,7 +91,8 @@ struct Layout {
   // saved
   size_t Z, reach, offset, perm, geo, col, saved_bytes;
   // workspace
-  size_t binof, keysF, kA, vA, kB, vB, hist, dtot, rpart, trec, prec, gpart, fplan, work_bytes;
+  size_t binof, keysF, kA, vA, kB, vB, geoA, colA, geoB, colB, hist, dtot, rpart, prec, gpart, fplan,
+      work_bytes;
 };
 
 inline Layout make_layout(const Geometry& g) {
@@ -112,10 +113,15 @@ inline Layout make_layout(const Geometry& g) {
   L.vA = o;     o = align_up(o + B * N * 4);
   L.kB = o;     o = align_up(o + B * N * 4);
   L.vB = o;     o = align_up(o + B * N * 4);
+  // point records between radix passes (the second set only with 3+ passes)
+  const size_t NB = g.npass >= 3 ? N : 0;
+  L.geoA = o;   o = align_up(o + B * N * 16);
+  L.colA = o;   o = align_up(o + B * N * size_t(g.CS) * 4);
+  L.geoB = o;   o = align_up(o + B * NB * 16);
+  L.colB = o;   o = align_up(o + B * NB * size_t(g.CS) * 4);
   L.hist = o;   o = align_up(o + B * size_t(256) * g.ntiles * 4);
   L.dtot = o;   o = align_up(o + B * size_t(256) * 4);
   L.rpart = o;  o = align_up(o + B * size_t(g.units256) * 4 + 4);
-  L.trec = o;   o = align_up(o + B * N * (4 + size_t(g.CS)) * 4);
   L.prec = o;   o = align_up(o + B * HW * size_t(g.CP) * 4);
   L.gpart = o;  o = align_up(o + B * size_t(g.units256) * 4 + 4);
   // forward work order: 64 counters (bucket sizes, work cursor), then
@@ -188,11 +194,12 @@ struct ImageView {
   // workspace
   int* binof;               // [N] bin key of each point (point order)
   int* keysF;               // [N] bin keys in sorted order
-  int* kA; int* vA; int* kB; int* vB;   // radix ping-pong buffers
+  int* kA; int* vA; int* kB; int* vB;   // radix ping-pong buffers: keys, point indices
+  float4* geoA; float* colA;            // and the point records (as geo, col)
+  float4* geoB; float* colB;
   int* hist;                // [256 * ntiles] per (digit, tile) counts, then offsets
   int* dtot;                // [256] per-digit totals of the current radix pass
   float* rpart;             // [units256] partial maxima of radius*sigma
-  float* trec;              // [N, 4 + CS] packed point records in point order
   float* prec;              // [H, W, CP] backward pixel records
   float* gpart;             // [units256] partial sums of dL/dsigma (shared sigma)
 };
@@ -228,7 +235,10 @@ __host__ __device__ inline ImageView image_of(const ImageView& v0, int b) {
   v.hist = shift(v0.hist, bb * 256 * size_t(v0.ntiles));
   v.dtot = shift(v0.dtot, bb * 256);
   v.rpart = shift(v0.rpart, bb * v0.units256);
-  v.trec = shift(v0.trec, bb * N * (4 + size_t(v0.CS)));
+  v.geoA = shift(v0.geoA, bb * N);
+  v.colA = shift(v0.colA, bb * N * v0.CS);
+  v.geoB = shift(v0.geoB, bb * N);
+  v.colB = shift(v0.colB, bb * N * v0.CS);
   v.prec = shift(v0.prec, bb * HW * v0.CP);
   v.gpart = shift(v0.gpart, bb * v0.units256);
   return v;
@@ -272,7 +282,10 @@ inline ImageView make_view(const Geometry& g, const Layout& L, void* saved, void
   v.hist = w ? reinterpret_cast<int*>(w + L.hist) : nullptr;
   v.dtot = w ? reinterpret_cast<int*>(w + L.dtot) : nullptr;
   v.rpart = w ? reinterpret_cast<float*>(w + L.rpart) : nullptr;
-  v.trec = w ? reinterpret_cast<float*>(w + L.trec) : nullptr;
+  v.geoA = w ? reinterpret_cast<float4*>(w + L.geoA) : nullptr;
+  v.colA = w ? reinterpret_cast<float*>(w + L.colA) : nullptr;
+  v.geoB = w ? reinterpret_cast<float4*>(w + L.geoB) : nullptr;
+  v.colB = w ? reinterpret_cast<float*>(w + L.colB) : nullptr;
   v.prec = w ? reinterpret_cast<float*>(w + L.prec) : nullptr;
   v.gpart = w ? reinterpret_cast<float*>(w + L.gpart) : nullptr;
   return v;

@@ -13,10 +13,10 @@
 //                  digit histograms of the first radix pass
 //   radix_hist / radix_scan / radix_scatter   (x npass; no radix_hist in
 //                  the first pass)
-//                  stable LSD radix sort of (key, point index) -> the
-//                  counting-sort order by bin, ties by point index
+//                  stable LSD radix sort of (key, point index, record)
+//                  -> the counting-sort order by bin, ties by point index,
+//                  and the point records (x, y, k, R2, values) in that order
 //   bin_finish     bin offsets from the sorted keys; per-image reach
-//   bin_gather     sorted point records (x, y, k, R2) and values
 //   fwd_plan       (single-call path) cost class of every forward unit, for
 //                  a heaviest-first launch order
 //   forward        the gather: per 8x8 pixel block, candidates from the bins
@@ -94,26 +94,25 @@ __device__ inline void wave_lds_sync() {
 // Binning: stable LSD radix sort of the bin keys (no global atomics)
 // ---------------------------------------------------------------------------
 
-// Values 4 .. CS-1 of point j's record (zero beyond C), for C > 4.
-__device__ inline void store_record_tail(const ImageView& v, int j) {
-  float4* rec = reinterpret_cast<float4*>(v.trec + (size_t)j * (4 + v.CS));
+// The record of point j: geo (x, y, k, R2) and its values padded to CS.
+__device__ inline float4 point_geo(const ImageView& v, int j) {
+  return make_geo(v.pos[j], sigma_of(v, j), v.radius);
+}
+__device__ inline float4 point_values4(const ImageView& v, int j, int c) {
   const float* src = v.values + (size_t)j * v.C;
-  for (int c = 4; c < v.CS; c += 4) {
-    float4 q;
-    q.x = c < v.C ? src[c] : 0.0f;
-    q.y = c + 1 < v.C ? src[c + 1] : 0.0f;
-    q.z = c + 2 < v.C ? src[c + 2] : 0.0f;
-    q.w = c + 3 < v.C ? src[c + 3] : 0.0f;
-    rec[1 + c / 4] = q;
-  }
+  float4 q;
+  q.x = c < v.C ? src[c] : 0.0f;
+  q.y = c + 1 < v.C ? src[c + 1] : 0.0f;
+  q.z = c + 2 < v.C ? src[c + 2] : 0.0f;
+  q.w = c + 3 < v.C ? src[c + 3] : 0.0f;
+  return q;
 }
 
-// unit = one radix tile of kRadixTile points: bin key of every point, its
-// packed record (x, y, k, R2, values) in point order, the tile's maximum of
-// radius*sigma and -- the first radix pass needs it -- the tile's histogram
-// of the lowest key digit.  lh: 256 ints of LDS.  The inputs of all the
-// tile's points are loaded before anything is stored (indices clamped into
-// the arrays), so the loads are not serialised behind the stores.
+// unit = one radix tile of kRadixTile points: bin key of every point, the
+// tile's maximum of radius*sigma and -- the first radix pass needs it -- the
+// tile's histogram of the lowest key digit.  lh: 256 ints of LDS.  With a
+// single bin (no radix pass) the point order is already sorted and the
+// sorted records are written here.
 __device__ inline void bin_keys(const ImageView& v, int tile, float* red4, int* lh) {
   const int t = threadIdx.x;
   const int width0 = v.npass > 0 ? min(v.dbits, v.kbits) : 0;
@@ -121,17 +120,11 @@ __device__ inline void bin_keys(const ImageView& v, int tile, float* red4, int* 
   const int j0 = tile * kRadixTile + t;
   float2 p[kRadixItems];
   float sg[kRadixItems];
-  float4 vals[kRadixItems];
 #pragma unroll
   for (int r = 0; r < kRadixItems; ++r) {
-    const int jc = min(j0 + r * 256, v.N - 1);
+    const int jc = min(j0 + r * 256, v.N - 1);  // clamped: no load behind a branch
     p[r] = v.pos[jc];
     sg[r] = sigma_of(v, jc);
-    const float* src = v.values + (size_t)jc * v.C;
-    vals[r].x = src[0];
-    vals[r].y = v.C > 1 ? src[1] : 0.0f;
-    vals[r].z = v.C > 2 ? src[2] : 0.0f;
-    vals[r].w = v.C > 3 ? src[3] : 0.0f;
   }
   lh[t] = 0;
   __syncthreads();
@@ -143,26 +136,22 @@ __device__ inline void bin_keys(const ImageView& v, int tile, float* red4, int* 
       const int key =
           bin_coord(p[r].y, v.inv_tile, v.nby) * v.nbx + bin_coord(p[r].x, v.inv_tile, v.nbx);
       v.binof[j] = key;
-      if (v.npass == 0) {  // a single bin: the identity order is already sorted
-        v.keysF[j] = key;
-        v.perm[j] = j;
-      } else {
-        atomicAdd(&lh[key & mask0], 1);
-      }
+      if (v.npass > 0) atomicAdd(&lh[key & mask0], 1);
       float rs = __fmul_rn(v.radius, sg[r]);
       if (!(rs >= 0.0f)) rs = 0.0f;  // caller contract violated; keep the reach sane
       rmax = fmaxf(rmax, rs);
-      // the point's record (x, y, k, R2, values) packed in point order, so
-      // the gather into bin order reads one record per point
-      float4* rec = reinterpret_cast<float4*>(v.trec + (size_t)j * (4 + v.CS));
-      rec[0] = make_geo(p[r], sg[r], v.radius);
-      rec[1] = vals[r];
     }
   }
-  if (v.CS > 4) {
-#pragma unroll
-    for (int r = 0; r < kRadixItems; ++r)
-      if (j0 + r * 256 < v.N) store_record_tail(v, j0 + r * 256);
+  if (v.npass == 0) {
+    for (int r = 0; r < kRadixItems; ++r) {
+      const int j = j0 + r * 256;
+      if (j >= v.N) continue;
+      v.keysF[j] = 0;
+      v.perm[j] = j;
+      v.geo[j] = make_geo(p[r], sg[r], v.radius);
+      float4* dst = reinterpret_cast<float4*>(v.col + (size_t)j * v.CS);
+      for (int c = 0; c < v.CS; c += 4) dst[c / 4] = point_values4(v, j, c);
+    }
   }
   __syncthreads();
   if (v.npass > 0 && t <= mask0) v.hist[t * v.ntiles + tile] = lh[t];
@@ -244,48 +233,47 @@ __device__ inline void radix_scan_digit(const ImageView& v, int p, int d, int* t
 }
 
 // LDS ints radix_scatter needs: wrun[4][256], base[256], tstart[256], tmp4,
-// and the tile's keys and values in digit order.
+// and the tile's keys and source slots in digit order.
 __host__ __device__ constexpr int radix_scatter_lds_ints() { return 6 * 256 + 4 + 2 * kRadixTile; }
 
-// unit = one tile: stable scatter of (key, value) by the pass's digit.  Each
-// wavefront ranks the 512 consecutive keys it owns in rounds of 64 (equal
-// digits by ballot -- multisplit -- and a per-wavefront running count per
-// digit in LDS); the wavefronts' counts then give every key its place in a
-// digit-ordered copy of the tile in LDS (wavefronts in index order, so equal
-// digits keep their input order), which is written out so that every digit's
-// keys form one contiguous run in the output.
+// unit = one tile: stable scatter of the tile's points by the pass's digit,
+// moving with each key its point index and record (geo, values) -- built
+// from the inputs in the first pass, so the last pass leaves the records in
+// bin order and no gather is needed.  Each wavefront ranks the
+// kRadixTile / 4 consecutive keys it owns in rounds of 64 (equal digits by ballot --
+// multisplit -- and a per-wavefront running count per digit in LDS); the
+// wavefronts' counts then give every key its place in a digit-ordered list of
+// the tile in LDS (wavefronts in index order, so equal digits keep their
+// input order), which is written out so that every digit's entries form one
+// contiguous run in the output.
 __device__ inline void radix_scatter(const ImageView& v, int p, int tile, int* lds) {
   int* wrun = lds;                 // [4][256]
   int* base = lds + 1024;          // [256]
   int* tstart = lds + 1280;        // [256]
   int* tmp4 = lds + 1536;          // [4]
   int* skey = lds + 1540;          // [kRadixTile]
-  int* sval = skey + kRadixTile;   // [kRadixTile]
+  int* ssrc = skey + kRadixTile;   // [kRadixTile] slot of the entry in the tile's input
   int shift, width;
   radix_pass_bits(v, p, &shift, &width);
   const int ndig = 1 << width, mask = ndig - 1;
-  const int* kin = p == 0 ? v.binof : (((p - 1) & 1) == 0 ? v.kA : v.kB);
-  const int* vin = p == 0 ? nullptr : (((p - 1) & 1) == 0 ? v.vA : v.vB);
-  const bool last = p == v.npass - 1;
-  int* kout = last ? v.keysF : ((p & 1) == 0 ? v.kA : v.kB);
-  int* vout = last ? v.perm : ((p & 1) == 0 ? v.vA : v.vB);
+  const bool first = p == 0, last = p == v.npass - 1;
+  const bool in_a = ((p - 1) & 1) == 0, out_a = (p & 1) == 0;
+  // buffer choice by value (selecting between fields through the view would
+  // make the compiler copy the view to scratch memory)
+  int* const kA = v.kA; int* const kB = v.kB; int* const vA = v.vA; int* const vB = v.vB;
+  float4* const geoA = v.geoA; float4* const geoB = v.geoB;
+  float* const colA = v.colA; float* const colB = v.colB;
+  const int* kin = first ? v.binof : (in_a ? kA : kB);
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
   const int t0 = tile * kRadixTile;
   const int tn = min(kRadixTile, v.N - t0);
-  // every global load of the tile is issued up front (the LDS fences below
-  // would otherwise hold each one back until it is needed)
-  // (indices clamped into the array, so that no load sits behind a branch)
-  int key[kRadixItems], val[kRadixItems], rk[kRadixItems];
-  const int i0 = t0 + wid * (kRadixTile / 4) + lane;
+  // every global load of the ranking is issued up front (the LDS fences
+  // below would otherwise hold each one back until it is needed; indices
+  // are clamped into the array so that no load sits behind a branch)
+  int key[kRadixItems], rk[kRadixItems];
+  const int s0 = wid * (kRadixTile / 4) + lane;  // this lane's first slot in the tile
 #pragma unroll
-  for (int r = 0; r < kRadixItems; ++r) key[r] = kin[min(i0 + r * 64, v.N - 1)];
-  if (vin) {
-#pragma unroll
-    for (int r = 0; r < kRadixItems; ++r) val[r] = vin[min(i0 + r * 64, v.N - 1)];
-  } else {
-#pragma unroll
-    for (int r = 0; r < kRadixItems; ++r) val[r] = i0 + r * 64;
-  }
+  for (int r = 0; r < kRadixItems; ++r) key[r] = kin[min(t0 + s0 + r * 64, v.N - 1)];
   const int dt = t < ndig ? v.dtot[t] : 0;
   const int th = t < ndig ? v.hist[t * v.ntiles + tile] : 0;
   // global start of each digit for this tile: digit base + tile offset
@@ -297,7 +285,7 @@ __device__ inline void radix_scatter(const ImageView& v, int p, int tile, int* l
   int* myrun = wrun + wid * 256;
 #pragma unroll
   for (int r = 0; r < kRadixItems; ++r) {
-    const bool valid = i0 + r * 64 < v.N;
+    const bool valid = s0 + r * 64 < tn;
     const int d = (key[r] >> shift) & mask;
     unsigned long long peers = __ballot(valid);
     for (int bit = 0; bit < width; ++bit) {
@@ -325,24 +313,74 @@ __device__ inline void radix_scatter(const ImageView& v, int p, int tile, int* l
   }
   tstart[t] = block_exclusive_scan256(tot, tmp4);
   __syncthreads();
-  // 3) the tile in digit order in LDS
+  // 3) the tile in digit order in LDS: key and input slot
 #pragma unroll
   for (int r = 0; r < kRadixItems; ++r) {
     if (rk[r] >= 0) {
       const int d = (key[r] >> shift) & mask;
       const int lpos = tstart[d] + myrun[d] + rk[r];
       skey[lpos] = key[r];
-      sval[lpos] = val[r];
+      ssrc[lpos] = s0 + r * 64;
     }
   }
   __syncthreads();
-  // 4) write out: consecutive entries of one digit go to consecutive places
-  for (int e = t; e < tn; e += 256) {
-    const int k = skey[e];
-    const int d = (k >> shift) & mask;
-    const int gpos = base[d] + e - tstart[d];
-    kout[gpos] = k;
-    vout[gpos] = sval[e];
+  // 4) write out: consecutive entries of one digit go to consecutive places;
+  // all loads of this thread's entries first, then the stores
+  int* const keysF = v.keysF; int* const perm = v.perm;
+  float4* const geo = v.geo; float* const col = v.col;
+  int* kout = last ? keysF : (out_a ? kA : kB);
+  int* jout = last ? perm : (out_a ? vA : vB);
+  float4* gout = last ? geo : (out_a ? geoA : geoB);
+  float* cout = last ? col : (out_a ? colA : colB);
+  const int* jin = in_a ? vA : vB;
+  const float4* gin = in_a ? geoA : geoB;
+  const float* cin = in_a ? colA : colB;
+  constexpr int kHalf = kRadixItems;  // entries per batch of loads
+  int epos[kRadixItems];
+#pragma unroll
+  for (int h = 0; h < kRadixItems; h += kHalf) {
+    int ek[kHalf], ej[kHalf];
+    float4 eg[kHalf], ec[kHalf];
+#pragma unroll
+    for (int q = 0; q < kHalf; ++q) {
+      const int e = min(t + (h + q) * 256, tn - 1);
+      ek[q] = skey[e];
+      const int src = t0 + ssrc[e];
+      const int d = (ek[q] >> shift) & mask;
+      epos[h + q] = base[d] + e - tstart[d];
+      if (first) {
+        ej[q] = src;
+        eg[q] = point_geo(v, src);
+        ec[q] = point_values4(v, src, 0);
+      } else {
+        ej[q] = jin[src];
+        eg[q] = gin[src];
+        ec[q] = reinterpret_cast<const float4*>(cin + (size_t)src * v.CS)[0];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kHalf; ++q) {
+      if (t + (h + q) * 256 < tn) {
+        const int g = epos[h + q];
+        kout[g] = ek[q];
+        jout[g] = ej[q];
+        gout[g] = eg[q];
+        reinterpret_cast<float4*>(cout + (size_t)g * v.CS)[0] = ec[q];
+      }
+    }
+  }
+  if (v.CS > 4) {  // values beyond the first four
+#pragma unroll
+    for (int r = 0; r < kRadixItems; ++r) {
+      const int e = t + r * 256;
+      if (e >= tn) continue;
+      const int src = t0 + ssrc[e];
+      float4* dst = reinterpret_cast<float4*>(cout + (size_t)epos[r] * v.CS);
+      for (int c = 4; c < v.CS; c += 4) {
+        dst[c / 4] = first ? point_values4(v, src, c)
+                           : reinterpret_cast<const float4*>(cin + (size_t)src * v.CS)[c / 4];
+      }
+    }
   }
   __syncthreads();
 }
@@ -363,18 +401,6 @@ __device__ inline void bin_finish(const ImageView& v, int unit, float* red4) {
     m = block_max(m, red4);
     if (threadIdx.x == 0) v.reach[0] = m;
   }
-}
-
-// unit = 256 sorted positions: the sorted records and values, each copied
-// from the packed record of its point
-__device__ inline void bin_gather(const ImageView& v, int unit) {
-  const int i = unit * 256 + threadIdx.x;
-  if (i >= v.N) return;
-  const int j = v.perm[i];
-  const float4* rec = reinterpret_cast<const float4*>(v.trec + (size_t)j * (4 + v.CS));
-  v.geo[i] = rec[0];
-  float4* dst = reinterpret_cast<float4*>(v.col + (size_t)i * v.CS);
-  for (int c = 0; c < v.CS / 4; ++c) dst[c] = rec[1 + c];
 }
 
 // number of positions bin_finish covers, in units of 256

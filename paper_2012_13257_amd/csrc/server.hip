@@ -39,7 +39,7 @@ enum Phase {
   PH_HIST0, PH_HIST1, PH_HIST2,
   PH_SCAN0, PH_SCAN1, PH_SCAN2,
   PH_SCAT0, PH_SCAT1, PH_SCAT2,
-  PH_FINISH, PH_GATHER, PH_FWD, PH_BPIX, PH_BPOINT, PH_BSIG,
+  PH_FINISH, PH_FWD, PH_BPIX, PH_BPOINT, PH_BSIG,
   PH_COUNT
 };
 
@@ -91,8 +91,6 @@ __global__ __launch_bounds__(256) void kj_phase(const JobTable* __restrict__ T) 
       dev::radix_scatter(v, PH - PH_SCAT0, local, lds_i);
     } else if constexpr (PH == PH_FINISH) {
       dev::bin_finish(v, local, red4);
-    } else if constexpr (PH == PH_GATHER) {
-      dev::bin_gather(v, local);
     } else if constexpr (PH == PH_FWD) {
       switch (T->ct[lo]) {
         case 1: dev::forward_block_q<1>(v, local, s_rec); break;
@@ -174,7 +172,6 @@ class GpuExecutor {
       enqueue_phase<PH_SCAN2>(x.dtab, x.stream);
       enqueue_phase<PH_SCAT2>(x.dtab, x.stream);
       enqueue_phase<PH_FINISH>(x.dtab, x.stream);
-      enqueue_phase<PH_GATHER>(x.dtab, x.stream);
       enqueue_phase<PH_FWD>(x.dtab, x.stream);
       enqueue_phase<PH_BPIX>(x.dtab, x.stream);
       enqueue_phase<PH_BPOINT>(x.dtab, x.stream);
@@ -234,7 +231,6 @@ class GpuExecutor {
         u[PH_SCAT0 + p] = on ? g.ntiles : 0;
       }
       u[PH_FINISH] = dev::finish_units(g.N);
-      u[PH_GATHER] = g.N > 0 ? g.units256 : 0;
       u[PH_FWD] = dev::fwd_units(g.bx_blocks, g.by_blocks);
       u[PH_BPIX] = bwd ? (g.H * g.W + 255) / 256 : 0;
       u[PH_BPOINT] = bwd && g.N > 0 ? g.units256 : 0;

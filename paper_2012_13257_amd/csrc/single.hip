@@ -62,10 +62,6 @@ __global__ __launch_bounds__(256) void k_fwd_plan(ImageView v0, int units, int t
   if (cls >= 0) fplan[64 + (size_t)cls * total + base[cls] + rank] = id;
 }
 
-__global__ __launch_bounds__(256) void k_bin_gather(ImageView v0) {
-  dev::bin_gather(image_of(v0, blockIdx.y), blockIdx.x);
-}
-
 // Forward gather.  Up to 4 channels: workgroup i takes the i-th unit of the
 // plan's work order, so the dispatcher starts the heaviest units first and
 // fills in the light ones as compute units free up (a unit's result does not
@@ -199,10 +195,6 @@ hipError_t launch_forward_all(const Geometry& g, const ImageView& v0, int* fplan
     ProfRange pr_("bin_finish", st);
     hipLaunchKernelGGL(k_bin_finish, dim3(dev::finish_units(g.N), g.B), dim3(256), 0, st, v0,
                        fplan);
-  }
-  if (g.N > 0) {
-    ProfRange pr_("bin_gather", st);
-    hipLaunchKernelGGL(k_bin_gather, dim3(g.units256, g.B), dim3(256), 0, st, v0);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

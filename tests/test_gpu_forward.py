@@ -124,9 +124,9 @@ def _densest_block(wl, b):
     return by * 8, bx * 8
 
 
-def _sampled_check(wl, n_random, seed):
-    say("forward sampled", wl.name)
-    out, saved, _, _ = run_forward(wl)
+def _sampled_check(wl, n_random, seed, tile=8):
+    say("forward sampled", wl.name, "tile", tile)
+    out, saved, _, _ = run_forward(wl, tile)
     out = out.cpu().numpy()
     Zg = saved_Z(saved).cpu().numpy()
     rng = np.random.default_rng(seed)
@@ -158,6 +158,22 @@ def test_forward_cfg3_sampled():
 
 def test_forward_cfg5_sampled():
     _sampled_check(synth.config5(), 192, 55)
+
+
+def test_three_radix_passes_bins_and_sampled_forward():
+    # 4-pixel bins on a 2047 x 2050 image: 513 x 512 bins need 18 key bits,
+    # so the sort takes three passes (and both sets of between-pass records)
+    wl = synth.random_workload(4711, 1, 60000, 2047, 2050, C=3, sigma=(0.5, 2.0), blob_frac=0.5,
+                               blob_std=(20.0, 80.0))
+    _check_bins(wl, 4)
+    _sampled_check(wl, 512, 77, tile=4)
+
+
+def test_single_bin_needs_no_radix_pass():
+    # a 7 x 6 image is one 8 x 8 bin: the point order is the sorted order
+    wl = synth.random_workload(4712, 2, 300, 7, 6, C=4, sigma=(0.5, 2.0))
+    _check_bins(wl)
+    _full_forward_check(wl)
 
 
 # ---------------------------------------------------------------------------
