@@ -805,24 +805,63 @@ __device__ inline void bwd_pixel(const ImageView& v, int unit) {
     dst[q] = make_float4(rec[4 * q], rec[4 * q + 1], rec[4 * q + 2], rec[4 * q + 3]);
 }
 
-// unit = 256 points in sorted order.  The block first regroups its points by
-// the size of their disk (so the lanes of a wavefront loop over similar
-// extents); each thread then walks its point's disk row by row -- the columns
-// of a row bounded by a conservative chord and visited without branching
-// (pixels outside the radius get w = 0, so the loads can be issued ahead),
-// the forward's radius test repeated bit for bit -- recomputes w_ij and
-// accumulates in registers; results go to the point's own index.  A point's
-// result does not depend on which lane computes it, and the shared-sigma
-// partial sum is taken in the original point order: the output is
-// deterministic.  lds: 256 + 32 ints.
+// Pixel records a workgroup of the adjoint can stage in LDS (36 KB).
+constexpr int kBwdStageF4 = 2304;
+
+// unit = 256 points in sorted order.  When the unit's points lie in one bin
+// row and the pixel records they can reach fit in kBwdStageF4 float4s, the
+// block first copies that window of records to LDS (one coalesced pass)
+// and the walk below reads LDS; otherwise it reads the records from global
+// memory.  The block then regroups its points by the size of their disk (so
+// the lanes of a wavefront loop over similar extents); each thread walks its
+// point's disk row by row -- the columns of a row bounded by a conservative
+// chord and visited without branching (pixels outside the radius get w = 0,
+// so the loads can be issued ahead), the forward's radius test repeated bit
+// for bit -- recomputes w_ij and accumulates in registers; results go to the
+// point's own index.  A point's result does not depend on which lane
+// computes it, and the shared-sigma partial sum is taken in the original
+// point order: the output is deterministic.  lds: 256 + 32 ints; stage:
+// kBwdStageF4 float4s.
 template <int CT>
-__device__ inline void bwd_point(const ImageView& v, int unit, float* red4, int* lds) {
+__device__ inline void bwd_point(const ImageView& v, int unit, float* red4, int* lds,
+                                 float4* stage) {
   constexpr int CS = CT < 4 ? 4 : CT;
   constexpr int CP = (CT + 1 + 3) / 4 * 4;
+  constexpr int CP4 = CP / 4;
   int* order = lds;            // [256] local point index by regrouped slot
   int* cls_n = lds + 256;      // [32]
   float* gs_l = reinterpret_cast<float*>(lds);
   const int base = unit * 256;
+  // the window of pixel records the unit's points can reach: bin columns
+  // [first, last] of one bin row, widened by the image's reach and by 3
+  // pixels for the groups of 4 below
+  // (bins recomputed from the saved sorted positions, as bin_keys made them)
+  int rx0 = 0, rx1 = -1, ry0 = 0, ry1 = -1;
+  {
+    const float4 gf = v.geo[base], gl = v.geo[min(base + 255, v.N - 1)];
+    const int byf = bin_coord(gf.y, v.inv_tile, v.nby), byl = bin_coord(gl.y, v.inv_tile, v.nby);
+    if (byf == byl) {
+      const int bxf = bin_coord(gf.x, v.inv_tile, v.nbx), bxl = bin_coord(gl.x, v.inv_tile, v.nbx);
+      const float Rh = conservative_reach(v.reach[0]);
+      const float T = (float)v.T;
+      const float x0 = floorf((float)bxf * T - Rh) - 3.0f;
+      const float x1 = ceilf((float)(bxl + 1) * T + Rh) + 3.0f;
+      const float y0 = floorf((float)byf * T - Rh), y1 = ceilf((float)(byf + 1) * T + Rh);
+      rx0 = (int)fmaxf(x0, 0.0f);
+      rx1 = (int)fminf(x1, (float)(v.W - 1));
+      ry0 = (int)fmaxf(y0, 0.0f);
+      ry1 = (int)fminf(y1, (float)(v.H - 1));
+    }
+  }
+  const int rw = rx1 - rx0 + 1, rh = ry1 - ry0 + 1;
+  const bool staged = rw > 0 && rh > 0 && rw * rh * CP4 <= kBwdStageF4;
+  if (staged) {
+    const int rowf4 = rw * CP4;
+    for (int i = threadIdx.x; i < rh * rowf4; i += 256) {
+      const int r = i / rowf4, c = i - r * rowf4;
+      stage[i] = reinterpret_cast<const float4*>(v.prec)[((size_t)(ry0 + r) * v.W + rx0) * CP4 + c];
+    }
+  }
   {
     const int tt = base + threadIdx.x;
     int cls = 0;
@@ -859,60 +898,77 @@ __device__ inline void bwd_point(const ImageView& v, int unit, float* red4, int*
     const float fuhi = fmaxf(fminf(floorf(g.x + Rh), (float)(v.W - 1)), -1.0f);
     const float fvlo = fminf(fmaxf(ceilf(g.y - Rh), 0.0f), (float)v.H);
     const float fvhi = fmaxf(fminf(floorf(g.y + Rh), (float)(v.H - 1)), -1.0f);
-    const int ulo = (int)fulo, uhi = (int)fuhi, vlo = (int)fvlo, vhi = (int)fvhi;
+    int vlo = (int)fvlo, vhi = (int)fvhi;
+    if (staged) {  // a point of the unit never leaves the window; invalid inputs are cut to it
+      vlo = max(vlo, ry0);
+      vhi = min(vhi, ry1);
+    }
     float gx = 0.0f, gy = 0.0f, gs = 0.0f;
     float gc[CT];
 #pragma unroll
     for (int k = 0; k < CT; ++k) gc[k] = 0.0f;
     const float R2m = g.w * (1.0f + 0x1p-20f);
-    for (int py = vlo; py <= vhi; ++py) {
-      const float dy = (float)py - g.y;
-      const float dyy = dy * dy;
-      // conservative chord of the disk on this row (v_sqrt_f32's error is far
-      // inside the margin), widened to a multiple of 4 pixels inside the image
-      // so that every row runs whole groups of 4; every pixel is visited
-      // without branching (pixels outside the radius get w = 0)
-      const float rr =
-          __builtin_amdgcn_sqrtf(fmaxf(R2m - dyy, 0.0f)) * (1.0f + 0x1p-10f) + 0x1p-10f;
-      const float fulo = fminf(fmaxf(ceilf(g.x - rr), 0.0f), (float)v.W);
-      const float fuhi = fmaxf(fminf(floorf(g.x + rr), (float)(v.W - 1)), -1.0f);
-      int ulo = (int)fulo, uhi = (int)fuhi;
-      const float4* prow = reinterpret_cast<const float4*>(v.prec + (size_t)py * v.W * CP);
-      auto pixel = [&](int px) {
-        const float dx = (float)px - g.x;
-        const float d2 = dx * dx + dyy;
-        float rec[CP];
+    // the disk walk; rec(py, px, q) returns float4 q of pixel (py, px)'s record
+    auto walk = [&](auto rec_of) {
+      for (int py = vlo; py <= vhi; ++py) {
+        const float dy = (float)py - g.y;
+        const float dyy = dy * dy;
+        // conservative chord of the disk on this row (v_sqrt_f32's error is
+        // far inside the margin), widened to a multiple of 4 pixels inside the
+        // image so that every row runs whole groups of 4; every pixel is
+        // visited without branching (pixels outside the radius get w = 0)
+        const float rr =
+            __builtin_amdgcn_sqrtf(fmaxf(R2m - dyy, 0.0f)) * (1.0f + 0x1p-10f) + 0x1p-10f;
+        const float fulo = fminf(fmaxf(ceilf(g.x - rr), 0.0f), (float)v.W);
+        const float fuhi = fmaxf(fminf(floorf(g.x + rr), (float)(v.W - 1)), -1.0f);
+        int ulo = (int)fulo, uhi = (int)fuhi;
+        auto pixel = [&](int px) {
+          const float dx = (float)px - g.x;
+          const float d2 = dx * dx + dyy;
+          float rec[CP];
 #pragma unroll
-        for (int q = 0; q < CP / 4; ++q) {
-          const float4 r4 = prow[(size_t)px * (CP / 4) + q];
-          rec[4 * q] = r4.x; rec[4 * q + 1] = r4.y; rec[4 * q + 2] = r4.z; rec[4 * q + 3] = r4.w;
-        }
-        float w = __builtin_amdgcn_exp2f(d2 * g.z);
-        w = (d2 <= g.w) ? w : 0.0f;
-        float A = -rec[CT];
+          for (int q = 0; q < CP4; ++q) {
+            const float4 r4 = rec_of(py, px, q);
+            rec[4 * q] = r4.x; rec[4 * q + 1] = r4.y; rec[4 * q + 2] = r4.z; rec[4 * q + 3] = r4.w;
+          }
+          float w = __builtin_amdgcn_exp2f(d2 * g.z);
+          w = (d2 <= g.w) ? w : 0.0f;
+          float A = -rec[CT];
 #pragma unroll
-        for (int k = 0; k < CT; ++k) {
-          A = __builtin_fmaf(rec[k], cc[k], A);
-          gc[k] = __builtin_fmaf(w, rec[k], gc[k]);
+          for (int k = 0; k < CT; ++k) {
+            A = __builtin_fmaf(rec[k], cc[k], A);
+            gc[k] = __builtin_fmaf(w, rec[k], gc[k]);
+          }
+          const float tA = A * w;
+          gx = __builtin_fmaf(tA, dx, gx);
+          gy = __builtin_fmaf(tA, dy, gy);
+          gs = __builtin_fmaf(tA, d2, gs);
+        };
+        const int n4 = (uhi - ulo + 4) & ~3;
+        if (uhi >= ulo && n4 <= v.W) {
+          // whole groups of 4 pixels, the window moved inside the image
+          ulo = min(ulo, v.W - n4);
+          if (staged && (ulo < rx0 || ulo + n4 - 1 > rx1)) continue;  // only for invalid inputs
+          for (int px = ulo; px < ulo + n4; px += 4) {
+            pixel(px);
+            pixel(px + 1);
+            pixel(px + 2);
+            pixel(px + 3);
+          }
+        } else {
+          if (staged) {
+            ulo = max(ulo, rx0);
+            uhi = min(uhi, rx1);
+          }
+          for (int px = ulo; px <= uhi; ++px) pixel(px);
         }
-        const float tA = A * w;
-        gx = __builtin_fmaf(tA, dx, gx);
-        gy = __builtin_fmaf(tA, dy, gy);
-        gs = __builtin_fmaf(tA, d2, gs);
-      };
-      const int n4 = (uhi - ulo + 4) & ~3;
-      if (uhi >= ulo && n4 <= v.W) {
-        // whole groups of 4 pixels, the window moved inside the image
-        ulo = min(ulo, v.W - n4);
-        for (int px = ulo; px < ulo + n4; px += 4) {
-          pixel(px);
-          pixel(px + 1);
-          pixel(px + 2);
-          pixel(px + 3);
-        }
-      } else {
-        for (int px = ulo; px <= uhi; ++px) pixel(px);
       }
+    };
+    if (staged) {
+      walk([&](int py, int px, int q) { return stage[((py - ry0) * rw + (px - rx0)) * CP4 + q]; });
+    } else {
+      const float4* prec4 = reinterpret_cast<const float4*>(v.prec);
+      walk([&](int py, int px, int q) { return prec4[((size_t)py * v.W + px) * CP4 + q]; });
     }
     const float inv_s2 = 1.0f / (sg * sg);
     if (v.grad_pos) reinterpret_cast<float2*>(v.grad_pos)[j] = make_float2(gx * inv_s2, gy * inv_s2);

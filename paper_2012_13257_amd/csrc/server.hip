@@ -62,7 +62,9 @@ struct PhaseLds {
                               : (PH == PH_BPOINT)                 ? 256 + 64
                               : (PH >= PH_HIST0 && PH <= PH_HIST2) || PH == PH_KEYS ? 256
                                                                   : 4;
-  static constexpr int f4 = PH == PH_FWD ? dev::fwd_quarter_lds_f4() : 1;
+  static constexpr int f4 = PH == PH_FWD ? dev::fwd_quarter_lds_f4()
+                            : PH == PH_BPOINT ? dev::kBwdStageF4
+                                              : 1;
 };
 
 template <int PH>
@@ -107,10 +109,10 @@ __global__ __launch_bounds__(256) void kj_phase(const JobTable* __restrict__ T) 
       }
     } else if constexpr (PH == PH_BPOINT) {
       switch (T->ct[lo]) {
-        case 1: dev::bwd_point<1>(v, local, red4, lds_i); break;
-        case 2: dev::bwd_point<2>(v, local, red4, lds_i); break;
-        case 3: dev::bwd_point<3>(v, local, red4, lds_i); break;
-        default: dev::bwd_point<4>(v, local, red4, lds_i); break;
+        case 1: dev::bwd_point<1>(v, local, red4, lds_i, s_rec); break;
+        case 2: dev::bwd_point<2>(v, local, red4, lds_i, s_rec); break;
+        case 3: dev::bwd_point<3>(v, local, red4, lds_i, s_rec); break;
+        default: dev::bwd_point<4>(v, local, red4, lds_i, s_rec); break;
       }
     } else if constexpr (PH == PH_BSIG) {
       dev::bwd_sigma_sum(v, red4);

@@ -110,9 +110,10 @@ template <int CT>
 __global__ __launch_bounds__(256) void k_bwd_point(ImageView v0, int per8) {
   __shared__ float red4[4];
   __shared__ int lds[256 + 64];
+  __shared__ float4 stage[dev::kBwdStageF4];
   const int unit = (blockIdx.x & 7) * per8 + (blockIdx.x >> 3);
   if ((int)(blockIdx.x >> 3) >= per8 || unit >= v0.units256) return;
-  dev::bwd_point<CT>(image_of(v0, blockIdx.y), unit, red4, lds);
+  dev::bwd_point<CT>(image_of(v0, blockIdx.y), unit, red4, lds, stage);
 }
 
 __global__ __launch_bounds__(256) void k_bwd_sigma_sum(ImageView v0) {
