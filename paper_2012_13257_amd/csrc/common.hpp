@@ -45,23 +45,23 @@ inline void radix_plan(int nb, int* npass, int* dbits, int* kbits) {
   *dbits = *npass ? (bits + *npass - 1) / *npass : 0;
 }
 
-// Forward work units (see forward_block_q): a unit is one 256-thread block
-// covering kUBW x kUBH blocks of 8x8 pixels, each evaluated by kFwdSplit
-// wavefronts.  The dispatcher hands consecutive workgroups to the 8 XCDs in
-// turn, so when units are launched in number order (the serving path) unit i
-// runs on XCD i % 8: units are numbered in groups of 8 that tile a 4 x 2
-// patch of units, and each XCD gets the same position in every patch -- a
-// regular lattice over the image, so a dense region is shared by all XCDs
-// instead of loading the few that own its columns.  (The single-call path
-// launches them in the order of a cost plan instead, heaviest first.)
-constexpr int kFwdSplit = 2;
-constexpr int kUBW = kFwdSplit == 1 ? 2 : kFwdSplit == 2 ? 2 : 1;
-constexpr int kUBH = kFwdSplit == 1 ? 2 : 1;
+// Forward work units (see forward_block_q): a unit is 2 x 2 blocks of 8x8
+// pixels, evaluated by one 256-thread workgroup in one of three modes: the
+// whole unit with one wavefront per block, or one half of it (blocks 0-1 or
+// 2-3) with two wavefronts per block -- dense units are split in two so that
+// no workgroup runs much longer than the rest.  The dispatcher hands
+// consecutive workgroups to the 8 XCDs in turn, so when work items are
+// launched in number order (the serving path) item i runs on XCD i % 8:
+// units are numbered in groups of 8 that tile a 4 x 2 patch of units, and
+// each XCD gets the same position in every patch -- a regular lattice over
+// the image, so a dense region is shared by all XCDs instead of loading the
+// few that own its columns.  (The single-call path launches the items in
+// the order of a cost plan instead, heaviest first.)
 constexpr int kPlanBuckets = 32;  // cost classes of the forward's work order
 struct FwdUnits {
   int ux, uy, stx;  // units per row / column, 4x2 patches per row
   __host__ __device__ FwdUnits(int bx_blocks, int by_blocks)
-      : ux((bx_blocks + kUBW - 1) / kUBW), uy((by_blocks + kUBH - 1) / kUBH), stx((ux + 3) / 4) {}
+      : ux((bx_blocks + 1) / 2), uy((by_blocks + 1) / 2), stx((ux + 3) / 4) {}
   __host__ __device__ int count() const { return stx * ((uy + 1) / 2) * 8; }
   // unit number -> unit coordinates; false for the padding units of the patches
   __host__ __device__ bool coords(int unit, int* cx, int* cy) const {
@@ -124,9 +124,9 @@ inline Layout make_layout(const Geometry& g) {
   L.rpart = o;  o = align_up(o + B * size_t(g.units256) * 4 + 4);
   L.prec = o;   o = align_up(o + B * HW * size_t(g.CP) * 4);
   L.gpart = o;  o = align_up(o + B * size_t(g.units256) * 4 + 4);
-  // forward work order: 64 counters (bucket sizes, work cursor), then
-  // kPlanBuckets lists of up to B * fwd_units unit numbers
-  L.fplan = o;  o = align_up(o + (64 + size_t(kPlanBuckets) * B * g.fwd_units) * 4);
+  // forward work order: 64 counters (list sizes), then kPlanBuckets lists of
+  // up to 2 * B * fwd_units work items
+  L.fplan = o;  o = align_up(o + (64 + size_t(kPlanBuckets) * 2 * B * g.fwd_units) * 4);
   L.work_bytes = o;
   return L;
 }
@@ -163,7 +163,7 @@ inline std::string make_geometry(const interp_problem* p, Geometry* g) {
   g->ntiles = (p->N + kRadixTile - 1) / kRadixTile;
   g->units256 = (p->N + 255) / 256;
   g->fwd_units = FwdUnits(g->bx_blocks, g->by_blocks).count();
-  if ((long long)g->fwd_units * g->B * kPlanBuckets >= (1LL << 31)) return "image too large";
+  if ((long long)g->fwd_units * g->B * kPlanBuckets * 2 >= (1LL << 31)) return "image too large";
   return "";
 }
 

@@ -515,9 +515,9 @@ __device__ inline void forward_tile(const ImageView& v, int tile, float4* s_geo 
 // Forward gather for up to 4 channels.  A wavefront evaluates one 8x8 pixel
 // block; a block's candidates are the records of the bins within reach --
 // one contiguous range of the sorted order per bin row -- taken as a single
-// concatenated sequence in 64-record chunks, and the kSplit wavefronts that
-// share a block take chunks w, w + kSplit, ... of it (a dense block is spread
-// over several SIMDs).  Within a wavefront the block is cut into four 4x4
+// concatenated sequence in 64-record chunks; when two wavefronts share a
+// block they take alternate chunks (a dense block is spread over two SIMDs).
+// Within a wavefront the block is cut into four 4x4
 // quarters: each candidate is tested against every quarter and appended to
 // the LDS list of each quarter its disk reaches, and a quarter's list is
 // evaluated four candidates at a time -- lane group g = lane / 16 takes list
@@ -525,7 +525,7 @@ __device__ inline void forward_tile(const ImageView& v, int tile, float4* s_geo 
 // a multiple of four with a null record: w = 0, values 0).  The next chunk's
 // records are loaded while the current one is processed.  Partial sums are
 // combined in a fixed order: the lane groups of a quarter as (g0 + g1) +
-// (g2 + g3), then the wavefronts of a block likewise.
+// (g2 + g3), then the two wavefronts of a block (if split) in order.
 constexpr int kQuarterList = 68;  // 64 hits + up to 3 padding entries
 __host__ __device__ inline constexpr int fwd_quarter_lds_f4() {
   return 4 * 4 * kQuarterList * 2;  // waves x quarters x entries x (geo, values)
@@ -555,33 +555,45 @@ __device__ inline void block_box(const ImageView& v, int bxb, int byb, int* u0, 
   *ve = min(*v0 + kBlockSide - 1, v.H - 1);
 }
 
-// Candidate records of the blocks of a forward unit (its cost estimate).
-__device__ inline int unit_candidates(const ImageView& v, int unit) {
+// Candidate records of each block of a forward unit (the cost estimate of
+// the plan); 0 for blocks outside the image and for padding units.
+__device__ inline void unit_candidates(const ImageView& v, int unit, int cost[4]) {
   int ucx, ucy;
-  if (!FwdUnits(v.bx_blocks, v.by_blocks).coords(unit, &ucx, &ucy)) return 0;
-  int n = 0;
-  for (int sb = 0; sb < 4 / kFwdSplit; ++sb) {
-    const int bxb = ucx * kUBW + sb % kUBW, byb = ucy * kUBH + sb / kUBW;
-    if (bxb >= v.bx_blocks || byb >= v.by_blocks) continue;
+  const bool in_grid = FwdUnits(v.bx_blocks, v.by_blocks).coords(unit, &ucx, &ucy);
+  for (int sb = 0; sb < 4; ++sb) {
+    cost[sb] = 0;
+    const int bxb = ucx * 2 + (sb & 1), byb = ucy * 2 + (sb >> 1);
+    if (!in_grid || bxb >= v.bx_blocks || byb >= v.by_blocks) continue;
     int u0, ue, v0, ve, bx_lo, bx_hi, by_lo, by_hi;
     block_box(v, bxb, byb, &u0, &ue, &v0, &ve);
     box_bins(v, u0, ue, v0, ve, &bx_lo, &bx_hi, &by_lo, &by_hi);
     for (int r = by_lo; r <= by_hi; ++r)
-      n += v.offset[r * v.nbx + bx_hi + 1] - v.offset[r * v.nbx + bx_lo];
+      cost[sb] += v.offset[r * v.nbx + bx_hi + 1] - v.offset[r * v.nbx + bx_lo];
   }
-  return n;
 }
 
+// A unit whose blocks hold kHeavyUnit or more candidate records is evaluated
+// as two halves (modes 1 and 2), any other unit whole (mode 0).  Both paths
+// take this decision the same way, so a pixel's sum is taken in the same
+// order alone and in a batch.
+constexpr int kHeavyUnit = 8192;
+__device__ inline bool unit_is_heavy(const int cost[4]) {
+  return cost[0] + cost[1] + cost[2] + cost[3] >= kHeavyUnit;
+}
+
+// mode 0: the whole unit, wavefront w on block w; mode 1 / 2: blocks 0-1 /
+// 2-3, wavefronts 2b and 2b+1 on the b-th of them.
 template <int CT>
-__device__ inline void forward_block_q(const ImageView& v, int unit, float4* s_rec) {
+__device__ inline void forward_block_q(const ImageView& v, int unit, int mode, float4* s_rec) {
   static_assert(CT <= 4, "the quarter lists hold the values of a record in one float4");
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int grp = lane >> 4, p = lane & 15;
-  const int sb = wid / kFwdSplit;  // this wavefront's block within the unit
-  const int phase = wid % kFwdSplit;
+  const int split = mode == 0 ? 1 : 2;                         // wavefronts per block
+  const int sb = mode == 0 ? wid : 2 * (mode - 1) + (wid >> 1);  // this wavefront's block
+  const int phase = mode == 0 ? 0 : (wid & 1);
   int ucx, ucy;
   const bool in_grid = FwdUnits(v.bx_blocks, v.by_blocks).coords(unit, &ucx, &ucy);
-  const int bxb = ucx * kUBW + sb % kUBW, byb = ucy * kUBH + sb / kUBW;
+  const int bxb = ucx * 2 + (sb & 1), byb = ucy * 2 + (sb >> 1);
   const bool active = in_grid && bxb < v.bx_blocks && byb < v.by_blocks;
   int u0, ue, v0, ve;
   block_box(v, active ? bxb : 0, active ? byb : 0, &u0, &ue, &v0, &ve);
@@ -658,10 +670,10 @@ __device__ inline void forward_block_q(const ImageView& v, int unit, float4* s_r
         c_n = cb[j];
       }
     }
-    for (; c0 < total; c0 += 64 * kFwdSplit) {
+    for (; c0 < total; c0 += 64 * split) {
       const bool in = c0 + lane < total;
       const float4 g = g_n, c = c_n;
-      const int cn = c0 + 64 * kFwdSplit;
+      const int cn = c0 + 64 * split;
       if (cn < total) {
         const int j = chunk_records(cn);
         if (cn + lane < total) {
@@ -742,19 +754,16 @@ __device__ inline void forward_block_q(const ImageView& v, int unit, float4* s_r
       part[k] = grp == q ? a : part[k];
     }
   }
-  // wavefronts of a block, through the (now free) list memory
-  if constexpr (kFwdSplit > 1) {
+  // the two wavefronts of a block (halves), through the (now free) list memory
+  if (mode != 0) {
     __syncthreads();
     float* red = reinterpret_cast<float*>(s_rec);
 #pragma unroll
     for (int k = 0; k <= CT; ++k) red[(k * 4 + wid) * 64 + lane] = part[k];
     __syncthreads();
-    const float* r0 = red + (wid - phase) * 64 + lane;
+    const float* r0 = red + (wid & ~1) * 64 + lane;
 #pragma unroll
-    for (int k = 0; k <= CT; ++k) {
-      const float* r = r0 + k * 256;
-      part[k] = kFwdSplit == 2 ? r[0] + r[64] : (r[0] + r[64]) + (r[128] + r[192]);
-    }
+    for (int k = 0; k <= CT; ++k) part[k] = r0[k * 256] + r0[k * 256 + 64];
   }
   const float Zo = part[CT];
   const int u = u0 + 4 * (grp & 1) + (p & 3), vv = v0 + 4 * (grp >> 1) + (p >> 2);

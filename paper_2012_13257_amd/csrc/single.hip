@@ -35,31 +35,47 @@ __global__ __launch_bounds__(256) void k_bin_finish(ImageView v0, int* fplan) {
   dev::bin_finish(image_of(v0, blockIdx.y), blockIdx.x, red4);
 }
 
-// Work order of the forward, heaviest units first: unit number id = image *
-// units + unit goes to the list of its cost class (floor(log2) + 1 of its
+// Work order of the forward, heaviest first.  A heavy unit (unit_is_heavy) is
+// split into two work items (blocks 0-1 and 2-3, two wavefronts per block),
+// any other unit is one item (one wavefront per block).  Item number = (image * units + unit) * 4 + mode;
+// each item goes to the list of its cost class (floor(log2) + 1 of its
 // candidate count, 0 for none).  fplan[0..31]: list sizes, lists from
-// fplan + 64 (kPlanBuckets x total).  A
-// workgroup ranks its units per class in LDS and reserves each class's slots
-// with one global atomic.  The order inside a list follows the atomics and
-// varies from run to run; the results do not depend on it (each unit computes
-// its pixels on its own).
+// fplan + 64 (kPlanBuckets x 2 * total).  A workgroup ranks its items per
+// class in LDS and reserves each class's slots with one global atomic.  The
+// order inside a list follows the atomics and varies from run to run; the
+// results do not depend on it (each item computes its pixels on its own).
+__device__ inline int cost_class(int cost) {
+  return cost == 0 ? 0 : min(kPlanBuckets - 1, 32 - __clz(cost));
+}
 __global__ __launch_bounds__(256) void k_fwd_plan(ImageView v0, int units, int total, int* fplan) {
   __shared__ int cnt[kPlanBuckets], base[kPlanBuckets];
   const int id = blockIdx.x * 256 + threadIdx.x;
   if (threadIdx.x < kPlanBuckets) cnt[threadIdx.x] = 0;
   __syncthreads();
-  int cls = -1, rank = 0;
+  int cls[2] = {-1, -1}, rank[2] = {0, 0}, item[2] = {0, 0};
   if (id < total) {
     const int b = id / units;
-    const int cost = dev::unit_candidates(image_of(v0, b), id - b * units);
-    cls = cost == 0 ? 0 : min(kPlanBuckets - 1, 32 - __clz(cost));
-    rank = atomicAdd(&cnt[cls], 1);
+    int c[4];
+    dev::unit_candidates(image_of(v0, b), id - b * units, c);
+    const int sum = c[0] + c[1] + c[2] + c[3];
+    if (dev::unit_is_heavy(c)) {
+      cls[0] = cost_class(c[0] + c[1]);
+      cls[1] = cost_class(c[2] + c[3]);
+      item[0] = id * 4 + 1;
+      item[1] = id * 4 + 2;
+    } else {
+      cls[0] = cost_class(sum);
+      item[0] = id * 4;
+    }
+    for (int k = 0; k < 2; ++k)
+      if (cls[k] >= 0) rank[k] = atomicAdd(&cnt[cls[k]], 1);
   }
   __syncthreads();
   if (threadIdx.x < kPlanBuckets && cnt[threadIdx.x] > 0)
     base[threadIdx.x] = atomicAdd(&fplan[threadIdx.x], cnt[threadIdx.x]);
   __syncthreads();
-  if (cls >= 0) fplan[64 + (size_t)cls * total + base[cls] + rank] = id;
+  for (int k = 0; k < 2; ++k)
+    if (cls[k] >= 0) fplan[64 + (size_t)cls[k] * 2 * total + base[cls[k]] + rank[k]] = item[k];
 }
 
 // Forward gather.  Up to 4 channels: workgroup i takes the i-th unit of the
@@ -80,12 +96,14 @@ __global__ __launch_bounds__(256) void k_forward_lpt(ImageView v0, int units, in
     if (lane >= o) incl += y;
   }
   const int w = blockIdx.x;
+  if (w >= __shfl(incl, kPlanBuckets - 1)) return;  // fewer items than the grid's upper bound
   const unsigned long long m = __ballot(lane < kPlanBuckets && w < incl);
   const int k = __ffsll((long long)m) - 1;  // the class list holding item w
   const int before = k > 0 ? __shfl(incl, k - 1) : 0;
-  const int id = fplan[64 + (size_t)(kPlanBuckets - 1 - k) * total + (w - before)];
+  const int item = fplan[64 + (size_t)(kPlanBuckets - 1 - k) * 2 * total + (w - before)];
+  const int id = item >> 2;
   const int b = id / units;
-  dev::forward_block_q<CT>(image_of(v0, b), id - b * units, s_rec);
+  dev::forward_block_q<CT>(image_of(v0, b), id - b * units, item & 3, s_rec);
 }
 
 template <int CT>
@@ -139,7 +157,7 @@ hipError_t launch_forward_t(const Geometry& g, const ImageView& v0, int* fplan, 
                          total, fplan);
     }
     ProfRange pr_("forward", st);
-    hipLaunchKernelGGL(k_forward_lpt<CT>, dim3((unsigned)total), dim3(256), 0, st, v0,
+    hipLaunchKernelGGL(k_forward_lpt<CT>, dim3((unsigned)(2 * total)), dim3(256), 0, st, v0,
                        g.fwd_units, total, fplan);
   } else {
     const int per = dev::fwd_tiles(g.bx_blocks, g.by_blocks);
