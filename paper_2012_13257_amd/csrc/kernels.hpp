@@ -30,6 +30,7 @@
 #pragma once
 
 #include <climits>
+#include <type_traits>
 
 #include "common.hpp"
 
@@ -918,7 +919,15 @@ __device__ inline void bwd_point(const ImageView& v, int unit, float* red4, int*
     for (int k = 0; k < CT; ++k) gc[k] = 0.0f;
     const float R2m = g.w * (1.0f + 0x1p-20f);
     // the disk walk; rec(py, px, q) returns float4 q of pixel (py, px)'s record
-    auto walk = [&](auto rec_of) {
+    // interior: the disk's box, widened by 3 pixels for the groups of 4, lies
+    // inside the image (and the staged window) for every lane of the
+    // wavefront, so the rows need no clamping
+    const bool interior_lane = !(t < v.N) || (g.x - Rh >= (float)max(rx0 * staged, 0) &&
+                                              g.x + Rh + 3.0f <= (float)(staged ? rx1 : v.W - 1) &&
+                                              g.y - Rh >= 0.0f && g.y + Rh <= (float)(v.H - 1));
+    const bool interior = __ballot(!interior_lane) == 0;
+    auto walk = [&](auto rec_of, auto interior_tag) {
+      constexpr bool kInterior = decltype(interior_tag)::value;
       for (int py = vlo; py <= vhi; ++py) {
         const float dy = (float)py - g.y;
         const float dyy = dy * dy;
@@ -928,9 +937,14 @@ __device__ inline void bwd_point(const ImageView& v, int unit, float* red4, int*
         // visited without branching (pixels outside the radius get w = 0)
         const float rr =
             __builtin_amdgcn_sqrtf(fmaxf(R2m - dyy, 0.0f)) * (1.0f + 0x1p-10f) + 0x1p-10f;
-        const float fulo = fminf(fmaxf(ceilf(g.x - rr), 0.0f), (float)v.W);
-        const float fuhi = fmaxf(fminf(floorf(g.x + rr), (float)(v.W - 1)), -1.0f);
-        int ulo = (int)fulo, uhi = (int)fuhi;
+        int ulo, uhi;
+        if constexpr (kInterior) {
+          ulo = (int)ceilf(g.x - rr);
+          uhi = (int)floorf(g.x + rr);
+        } else {
+          ulo = (int)fminf(fmaxf(ceilf(g.x - rr), 0.0f), (float)v.W);
+          uhi = (int)fmaxf(fminf(floorf(g.x + rr), (float)(v.W - 1)), -1.0f);
+        }
         auto pixel = [&](int px) {
           const float dx = (float)px - g.x;
           const float d2 = dx * dx + dyy;
@@ -954,7 +968,15 @@ __device__ inline void bwd_point(const ImageView& v, int unit, float* red4, int*
           gs = __builtin_fmaf(tA, d2, gs);
         };
         const int n4 = (uhi - ulo + 4) & ~3;
-        if (uhi >= ulo && n4 <= v.W) {
+        if constexpr (kInterior) {
+          // the chord (n4 = 0 when it is empty) and its padding are inside
+          for (int px = ulo; px < ulo + n4; px += 4) {
+            pixel(px);
+            pixel(px + 1);
+            pixel(px + 2);
+            pixel(px + 3);
+          }
+        } else if (uhi >= ulo && n4 <= v.W) {
           // whole groups of 4 pixels, the window moved inside the image
           ulo = min(ulo, v.W - n4);
           if (staged && (ulo < rx0 || ulo + n4 - 1 > rx1)) continue;  // only for invalid inputs
@@ -973,11 +995,19 @@ __device__ inline void bwd_point(const ImageView& v, int unit, float* red4, int*
         }
       }
     };
+    auto from_stage = [&](int py, int px, int q) {
+      return stage[((py - ry0) * rw + (px - rx0)) * CP4 + q];
+    };
+    const float4* prec4 = reinterpret_cast<const float4*>(v.prec);
+    auto from_global = [&](int py, int px, int q) {
+      return prec4[((size_t)py * v.W + px) * CP4 + q];
+    };
+    using Yes = std::integral_constant<bool, true>;
+    using No = std::integral_constant<bool, false>;
     if (staged) {
-      walk([&](int py, int px, int q) { return stage[((py - ry0) * rw + (px - rx0)) * CP4 + q]; });
+      if (interior) walk(from_stage, Yes{}); else walk(from_stage, No{});
     } else {
-      const float4* prec4 = reinterpret_cast<const float4*>(v.prec);
-      walk([&](int py, int px, int q) { return prec4[((size_t)py * v.W + px) * CP4 + q]; });
+      if (interior) walk(from_global, Yes{}); else walk(from_global, No{});
     }
     const float inv_s2 = 1.0f / (sg * sg);
     if (v.grad_pos) reinterpret_cast<float2*>(v.grad_pos)[j] = make_float2(gx * inv_s2, gy * inv_s2);
