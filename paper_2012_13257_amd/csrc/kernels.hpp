@@ -643,45 +643,41 @@ __device__ inline void forward_block_q(const ImageView& v, int unit, int mode, f
       const int y = __shfl_up(incl, o);
       if (lane >= o) incl += y;
     }
-    const int total = __builtin_amdgcn_readlane(incl, 63);
-    // Record index of position t of the concatenation: s_r + t - excl_r for
-    // the row r with excl_r <= t < incl_r.  Positions are visited in
-    // increasing order, so a wave-uniform row cursor `rc` (the row holding the
-    // first position of the current chunk) only moves forward.
-    const int ex_l = incl - len, base_l = s_r - ex_l;
-    int rc = 0;
-    auto chunk_records = [&](int c) {
-      while (__builtin_amdgcn_readlane(incl, rc) <= c) ++rc;
-      const int t = c + lane;
-      int j = __builtin_amdgcn_readlane(base_l, rc) + t;
-      for (int r = rc + 1; r < nr; ++r) {
-        const int ex = __builtin_amdgcn_readlane(ex_l, r);
-        if (ex >= c + 64) break;
-        j = t >= ex ? __builtin_amdgcn_readlane(base_l, r) + t : j;
-      }
-      return j;
+    (void)incl;
+    // Chunk cursor (wave-uniform): row r of the group, offset c in it, the
+    // row's first record rs and length rn.  Chunks are 64 records of one row;
+    // when two wavefronts share the block they take alternate chunks.
+    struct Cursor {
+      int r, c, rs, rn;
     };
-
-    int c0 = phase * 64;
+    auto advance = [&](Cursor& k) {
+      k.c += 64;
+      while (k.c >= k.rn) {
+        if (++k.r >= nr) return;
+        k.c = 0;
+        k.rs = __builtin_amdgcn_readlane(s_r, k.r);
+        k.rn = __builtin_amdgcn_readlane(len, k.r);
+      }
+    };
+    Cursor cur{-1, -64, 0, 0};
+    advance(cur);
+    if (phase) advance(cur);
     float4 g_n = zero4, c_n = zero4;
-    if (c0 < total) {
-      const int j = chunk_records(c0);
-      if (c0 + lane < total) {
-        g_n = gb[j];
-        c_n = cb[j];
-      }
+    if (cur.r < nr && cur.c + lane < cur.rn) {
+      g_n = gb[cur.rs + cur.c + lane];
+      c_n = cb[cur.rs + cur.c + lane];
     }
-    for (; c0 < total; c0 += 64 * split) {
-      const bool in = c0 + lane < total;
+    while (cur.r < nr) {
+      const bool in = cur.c + lane < cur.rn;
       const float4 g = g_n, c = c_n;
-      const int cn = c0 + 64 * split;
-      if (cn < total) {
-        const int j = chunk_records(cn);
-        if (cn + lane < total) {
-          g_n = gb[j];
-          c_n = cb[j];
-        }
+      Cursor nxt = cur;
+      advance(nxt);
+      if (split == 2) advance(nxt);
+      if (nxt.r < nr && nxt.c + lane < nxt.rn) {
+        g_n = gb[nxt.rs + nxt.c + lane];
+        c_n = cb[nxt.rs + nxt.c + lane];
       }
+      cur = nxt;
       // disk of the candidate against the box of each quarter (conservative)
       const float lim = g.w * 1.001f + 1e-6f;
       const float exl = fmaxf(fmaxf(fu0 - g.x, g.x - ful), 0.0f);
