@@ -94,17 +94,19 @@ __global__ __launch_bounds__(256) void kj_phase(const JobTable* __restrict__ T) 
     } else if constexpr (PH == PH_FINISH) {
       dev::bin_finish(v, local, red4);
     } else if constexpr (PH == PH_FWD) {
-      // two items per unit: a heavy unit's halves, or the whole unit and nothing
-      const int unit = local >> 1, half = local & 1;
+      // one item per unit, evaluated as the single-call path does: a heavy
+      // unit as its two halves (one after the other), any other whole
       int c[4];
-      dev::unit_candidates(v, unit, c);
-      const int mode = dev::unit_is_heavy(c) ? 1 + half : (half == 0 ? 0 : -1);
-      if (mode >= 0) {
+      dev::unit_candidates(v, local, c);
+      const bool heavy = dev::unit_is_heavy(c);
+      for (int h = 0; h < (heavy ? 2 : 1); ++h) {
+        const int mode = heavy ? 1 + h : 0;
+        if (h) __syncthreads();  // the lists of the first half are free again
         switch (T->ct[lo]) {
-          case 1: dev::forward_block_q<1>(v, unit, mode, s_rec); break;
-          case 2: dev::forward_block_q<2>(v, unit, mode, s_rec); break;
-          case 3: dev::forward_block_q<3>(v, unit, mode, s_rec); break;
-          default: dev::forward_block_q<4>(v, unit, mode, s_rec); break;
+          case 1: dev::forward_block_q<1>(v, local, mode, s_rec); break;
+          case 2: dev::forward_block_q<2>(v, local, mode, s_rec); break;
+          case 3: dev::forward_block_q<3>(v, local, mode, s_rec); break;
+          default: dev::forward_block_q<4>(v, local, mode, s_rec); break;
         }
       }
     } else if constexpr (PH == PH_BPIX) {
@@ -240,7 +242,7 @@ class GpuExecutor {
         u[PH_SCAT0 + p] = on ? g.ntiles : 0;
       }
       u[PH_FINISH] = dev::finish_units(g.N);
-      u[PH_FWD] = 2 * dev::fwd_units(g.bx_blocks, g.by_blocks);  // both halves of every unit
+      u[PH_FWD] = dev::fwd_units(g.bx_blocks, g.by_blocks);
       u[PH_BPIX] = bwd ? (g.H * g.W + 255) / 256 : 0;
       u[PH_BPOINT] = bwd && g.N > 0 ? g.units256 : 0;
       u[PH_BSIG] = bwd && !g.per_point && r.grad_sigma ? 1 : 0;
