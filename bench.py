@@ -131,8 +131,7 @@ def time_steps(fn, steps: int, warmup: int, profile: bool):
     kernels = {}
     if profile:
         for name in ("bin_keys", "radix_hist", "radix_scan", "radix_scatter", "bin_finish",
-                     "bin_gather", "fwd_plan", "forward", "bwd_pixel", "bwd_point",
-                     "bwd_sigma_sum"):
+                     "fwd_plan", "forward", "bwd_pixel", "bwd_point", "bwd_sigma_sum"):
             tot, n = _lib.profile_read(name)
             if n:
                 kernels[name] = {"avg_us": 1000.0 * tot / n, "launches": n}

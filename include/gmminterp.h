@@ -145,8 +145,8 @@ const char* interp_last_error(void);
  * interp_profile_read waits for the recorded kernels and returns, summed over
  * the kernels whose name starts with `prefix` ("" for all), the total
  * duration in milliseconds and the number of launches.  Kernel names:
- * bin_keys, radix_hist, radix_scan, radix_scatter, bin_finish, bin_gather,
- * fwd_plan, forward, bwd_pixel, bwd_point, bwd_sigma_sum. */
+ * bin_keys, radix_hist, radix_scan, radix_scatter, bin_finish, fwd_plan,
+ * forward, bwd_pixel, bwd_point, bwd_sigma_sum. */
 int interp_profile_enable(int on);
 int interp_profile_read(const char* prefix, double* total_ms, int64_t* launches);
 
