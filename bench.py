@@ -40,12 +40,15 @@ FORWARD_PROFILE = os.path.join(ROOT, "profiles", "forward_1024x1024_n1M_c3.md")
 
 
 def forward_source_hash() -> str:
-    """sha256 of the sources the forward kernel is built from."""
+    """sha256 of the code (comments and blank space removed) of the sources
+    the forward kernel is built from."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in FORWARD_SOURCES:
-        with open(os.path.join(ROOT, "paper_2012_13257_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2012_13257_amd", "csrc", f)) as fh:
+            code = re.sub(r"//[^\n]*", "", fh.read())
+        h.update(" ".join(code.split()).encode())
     return h.hexdigest()
 
 

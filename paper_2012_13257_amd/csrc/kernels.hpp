@@ -515,11 +515,10 @@ __device__ inline void forward_tile(const ImageView& v, int tile, float4* s_geo 
 
 // Forward gather for up to 4 channels.  A wavefront evaluates one 8x8 pixel
 // block; a block's candidates are the records of the bins within reach --
-// one contiguous range of the sorted order per bin row -- taken as a single
-// concatenated sequence in 64-record chunks; when two wavefronts share a
-// block they take alternate chunks (a dense block is spread over two SIMDs).
-// Within a wavefront the block is cut into four 4x4
-// quarters: each candidate is tested against every quarter and appended to
+// one contiguous range of the sorted order per bin row -- taken 64 records
+// of one row at a time; when two wavefronts share a block they take
+// alternate chunks (a dense block is spread over two SIMDs).  Within a
+// wavefront the block is cut into four 4x4 quarters: each candidate is tested against every quarter and appended to
 // the LDS list of each quarter its disk reaches, and a quarter's list is
 // evaluated four candidates at a time -- lane group g = lane / 16 takes list
 // entries g, g+4, ... for pixel lane % 16 of the quarter (lists are padded to
