@@ -426,7 +426,7 @@ template <int CT>
 __device__ inline void forward_tile(const ImageView& v, int tile, float4* s_geo /*[4][64]*/,
                                     float4* s_col /*[4][64*CS/4]*/) {
   constexpr int CS = CT < 4 ? 4 : CT;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wgx = fwd_tiles_x(v.bx_blocks);
   const int ty = tile / wgx, tx = tile - ty * wgx;
   const int u0 = (2 * tx + (wid & 1)) * kBlockSide;
@@ -526,7 +526,12 @@ __device__ inline void forward_tile(const ImageView& v, int tile, float4* s_geo 
 // records are loaded while the current one is processed.  Partial sums are
 // combined in a fixed order: the lane groups of a quarter as (g0 + g1) +
 // (g2 + g3), then the two wavefronts of a block (if split) in order.
-constexpr int kQuarterList = 68;  // 64 hits + up to 3 padding entries
+// A chunk has at most 64 candidates, so a list of n <= 64 hits padded to a
+// multiple of four never exceeds 64 entries; 64 x 32 B x 4 quarters x 4
+// wavefronts = 32 KB of LDS per workgroup lets five workgroups share a
+// compute unit's 160 KB.
+constexpr int kQuarterList = 64;
+static_assert(kQuarterList >= 64 && kQuarterList % 4 == 0, "a list holds a whole padded chunk");
 __host__ __device__ inline constexpr int fwd_quarter_lds_f4() {
   return 4 * 4 * kQuarterList * 2;  // waves x quarters x entries x (geo, values)
 }
@@ -586,7 +591,7 @@ __device__ inline bool unit_is_heavy(const int cost[4]) {
 template <int CT>
 __device__ inline void forward_block_q(const ImageView& v, int unit, int mode, float4* s_rec) {
   static_assert(CT <= 4, "the quarter lists hold the values of a record in one float4");
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int grp = lane >> 4, p = lane & 15;
   const int split = mode == 0 ? 1 : 2;                         // wavefronts per block
   const int sb = mode == 0 ? wid : 2 * (mode - 1) + (wid >> 1);  // this wavefront's block
@@ -812,6 +817,11 @@ __device__ inline void bwd_pixel(const ImageView& v, int unit) {
 
 // Pixel records a workgroup of the adjoint can stage in LDS (36 KB).
 constexpr int kBwdStageF4 = 2304;
+// The adjoint walks each row of a disk in whole groups of kBwdGroup pixels
+// (padding pixels get w = 0).  Groups of 2 pad fewer pixels on the short
+// chords of small disks but measured slower than groups of 4, whose four
+// independent weights keep more work in flight per loop trip.
+constexpr int kBwdGroup = 4;
 
 // unit = 256 points in sorted order.  When the unit's points lie in one bin
 // row and the pixel records they can reach fit in kBwdStageF4 float4s, the
@@ -838,8 +848,8 @@ __device__ inline void bwd_point(const ImageView& v, int unit, float* red4, int*
   float* gs_l = reinterpret_cast<float*>(lds);
   const int base = unit * 256;
   // the window of pixel records the unit's points can reach: bin columns
-  // [first, last] of one bin row, widened by the image's reach and by 3
-  // pixels for the groups of 4 below
+  // [first, last] of one bin row, widened by the image's reach and by
+  // kBwdGroup - 1 pixels for the groups below
   // (bins recomputed from the saved sorted positions, as bin_keys made them)
   int rx0 = 0, rx1 = -1, ry0 = 0, ry1 = -1;
   {
@@ -849,8 +859,8 @@ __device__ inline void bwd_point(const ImageView& v, int unit, float* red4, int*
       const int bxf = bin_coord(gf.x, v.inv_tile, v.nbx), bxl = bin_coord(gl.x, v.inv_tile, v.nbx);
       const float Rh = conservative_reach(v.reach[0]);
       const float T = (float)v.T;
-      const float x0 = floorf((float)bxf * T - Rh) - 3.0f;
-      const float x1 = ceilf((float)(bxl + 1) * T + Rh) + 3.0f;
+      const float x0 = floorf((float)bxf * T - Rh) - (float)(kBwdGroup - 1);
+      const float x1 = ceilf((float)(bxl + 1) * T + Rh) + (float)(kBwdGroup - 1);
       const float y0 = floorf((float)byf * T - Rh), y1 = ceilf((float)(byf + 1) * T + Rh);
       rx0 = (int)fmaxf(x0, 0.0f);
       rx1 = (int)fminf(x1, (float)(v.W - 1));
@@ -914,11 +924,13 @@ __device__ inline void bwd_point(const ImageView& v, int unit, float* red4, int*
     for (int k = 0; k < CT; ++k) gc[k] = 0.0f;
     const float R2m = g.w * (1.0f + 0x1p-20f);
     // the disk walk; rec(py, px, q) returns float4 q of pixel (py, px)'s record
-    // interior: the disk's box, widened by 3 pixels for the groups of 4, lies
-    // inside the image (and the staged window) for every lane of the
+    // interior: the disk's box, widened by G - 1 pixels for the groups of G,
+    // lies inside the image (and the staged window) for every lane of the
     // wavefront, so the rows need no clamping
+    constexpr int G = kBwdGroup;
     const bool interior_lane = !(t < v.N) || (g.x - Rh >= (float)max(rx0 * staged, 0) &&
-                                              g.x + Rh + 3.0f <= (float)(staged ? rx1 : v.W - 1) &&
+                                              g.x + Rh + (float)(G - 1) <=
+                                                  (float)(staged ? rx1 : v.W - 1) &&
                                               g.y - Rh >= 0.0f && g.y + Rh <= (float)(v.H - 1));
     const bool interior = __ballot(!interior_lane) == 0;
     auto walk = [&](auto rec_of, auto interior_tag) {
@@ -927,9 +939,9 @@ __device__ inline void bwd_point(const ImageView& v, int unit, float* red4, int*
         const float dy = (float)py - g.y;
         const float dyy = dy * dy;
         // conservative chord of the disk on this row (v_sqrt_f32's error is
-        // far inside the margin), widened to a multiple of 4 pixels inside the
-        // image so that every row runs whole groups of 4; every pixel is
-        // visited without branching (pixels outside the radius get w = 0)
+        // far inside the margin), widened to a multiple of G pixels inside the
+        // image so that every row runs whole groups; every pixel is visited
+        // without branching (pixels outside the radius get w = 0)
         const float rr =
             __builtin_amdgcn_sqrtf(fmaxf(R2m - dyy, 0.0f)) * (1.0f + 0x1p-10f) + 0x1p-10f;
         int ulo, uhi;
@@ -940,8 +952,10 @@ __device__ inline void bwd_point(const ImageView& v, int unit, float* red4, int*
           ulo = (int)fminf(fmaxf(ceilf(g.x - rr), 0.0f), (float)v.W);
           uhi = (int)fmaxf(fminf(floorf(g.x + rr), (float)(v.W - 1)), -1.0f);
         }
-        auto pixel = [&](int px) {
-          const float dx = (float)px - g.x;
+        // px is the pixel column and fpx the same integer as a float (exact:
+        // columns stay far below 2^24), so no conversion per pixel
+        auto pixel = [&](int px, float fpx) {
+          const float dx = fpx - g.x;
           const float d2 = dx * dx + dyy;
           float rec[CP];
 #pragma unroll
@@ -962,31 +976,28 @@ __device__ inline void bwd_point(const ImageView& v, int unit, float* red4, int*
           gy = __builtin_fmaf(tA, dy, gy);
           gs = __builtin_fmaf(tA, d2, gs);
         };
-        const int n4 = (uhi - ulo + 4) & ~3;
+        auto groups = [&](int lo, int n) {  // n: a multiple of G
+          float fpx = (float)lo;
+          for (int px = lo; px < lo + n; px += G) {
+#pragma unroll
+            for (int i = 0; i < G; ++i) pixel(px + i, fpx + (float)i);
+            fpx += (float)G;
+          }
+        };
+        const int ng = (uhi - ulo + G) & ~(G - 1);
         if constexpr (kInterior) {
-          // the chord (n4 = 0 when it is empty) and its padding are inside
-          for (int px = ulo; px < ulo + n4; px += 4) {
-            pixel(px);
-            pixel(px + 1);
-            pixel(px + 2);
-            pixel(px + 3);
-          }
-        } else if (uhi >= ulo && n4 <= v.W) {
-          // whole groups of 4 pixels, the window moved inside the image
-          ulo = min(ulo, v.W - n4);
-          if (staged && (ulo < rx0 || ulo + n4 - 1 > rx1)) continue;  // only for invalid inputs
-          for (int px = ulo; px < ulo + n4; px += 4) {
-            pixel(px);
-            pixel(px + 1);
-            pixel(px + 2);
-            pixel(px + 3);
-          }
+          groups(ulo, ng);  // the chord (ng = 0 when it is empty) and its padding are inside
+        } else if (uhi >= ulo && ng <= v.W) {
+          // whole groups of G pixels, the window moved inside the image
+          ulo = min(ulo, v.W - ng);
+          if (staged && (ulo < rx0 || ulo + ng - 1 > rx1)) continue;  // only for invalid inputs
+          groups(ulo, ng);
         } else {
           if (staged) {
             ulo = max(ulo, rx0);
             uhi = min(uhi, rx1);
           }
-          for (int px = ulo; px <= uhi; ++px) pixel(px);
+          for (int px = ulo; px <= uhi; ++px) pixel(px, (float)px);
         }
       }
     };

@@ -98,8 +98,10 @@ __global__ __launch_bounds__(256) void k_forward_lpt(ImageView v0, int units, in
   const int w = blockIdx.x;
   if (w >= __shfl(incl, kPlanBuckets - 1)) return;  // fewer items than the grid's upper bound
   const unsigned long long m = __ballot(lane < kPlanBuckets && w < incl);
-  const int k = __ffsll((long long)m) - 1;  // the class list holding item w
-  const int before = k > 0 ? __shfl(incl, k - 1) : 0;
+  // k and before are wave-uniform: taken into scalar registers, the item is a
+  // scalar load and the whole block walk below runs on scalar control flow
+  const int k = __builtin_amdgcn_readfirstlane(__ffsll((long long)m) - 1);  // class of item w
+  const int before = __builtin_amdgcn_readfirstlane(k > 0 ? __shfl(incl, k - 1) : 0);
   const int item = fplan[64 + (size_t)(kPlanBuckets - 1 - k) * 2 * total + (w - before)];
   const int id = item >> 2;
   const int b = id / units;
