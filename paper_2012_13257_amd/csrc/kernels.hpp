@@ -560,21 +560,23 @@ __device__ inline void block_box(const ImageView& v, int bxb, int byb, int* u0, 
   *ve = min(*v0 + kBlockSide - 1, v.H - 1);
 }
 
-// Candidate records of each block of a forward unit (the cost estimate of
-// the plan); 0 for blocks outside the image and for padding units.
-__device__ inline void unit_candidates(const ImageView& v, int unit, int cost[4]) {
+// Candidate records of block sb (0..3) of a forward unit (the cost estimate
+// of the plan); 0 for blocks outside the image and for padding units.
+__device__ inline int block_candidates(const ImageView& v, int unit, int sb) {
   int ucx, ucy;
   const bool in_grid = FwdUnits(v.bx_blocks, v.by_blocks).coords(unit, &ucx, &ucy);
-  for (int sb = 0; sb < 4; ++sb) {
-    cost[sb] = 0;
-    const int bxb = ucx * 2 + (sb & 1), byb = ucy * 2 + (sb >> 1);
-    if (!in_grid || bxb >= v.bx_blocks || byb >= v.by_blocks) continue;
-    int u0, ue, v0, ve, bx_lo, bx_hi, by_lo, by_hi;
-    block_box(v, bxb, byb, &u0, &ue, &v0, &ve);
-    box_bins(v, u0, ue, v0, ve, &bx_lo, &bx_hi, &by_lo, &by_hi);
-    for (int r = by_lo; r <= by_hi; ++r)
-      cost[sb] += v.offset[r * v.nbx + bx_hi + 1] - v.offset[r * v.nbx + bx_lo];
-  }
+  const int bxb = ucx * 2 + (sb & 1), byb = ucy * 2 + (sb >> 1);
+  if (!in_grid || bxb >= v.bx_blocks || byb >= v.by_blocks) return 0;
+  int u0, ue, v0, ve, bx_lo, bx_hi, by_lo, by_hi;
+  block_box(v, bxb, byb, &u0, &ue, &v0, &ve);
+  box_bins(v, u0, ue, v0, ve, &bx_lo, &bx_hi, &by_lo, &by_hi);
+  int cost = 0;
+  for (int r = by_lo; r <= by_hi; ++r)
+    cost += v.offset[r * v.nbx + bx_hi + 1] - v.offset[r * v.nbx + bx_lo];
+  return cost;
+}
+__device__ inline void unit_candidates(const ImageView& v, int unit, int cost[4]) {
+  for (int sb = 0; sb < 4; ++sb) cost[sb] = block_candidates(v, unit, sb);
 }
 
 // A unit whose blocks hold kHeavyUnit or more candidate records is evaluated

@@ -62,16 +62,25 @@ __global__ __launch_bounds__(256) void k_bin_finish(ImageView v0, int* fplan) {
 __device__ inline int cost_class(int cost) {
   return cost == 0 ? 0 : min(kPlanBuckets - 1, 32 - __clz(cost));
 }
+// Four threads per unit (one per block, lanes 4u .. 4u+3 of a wavefront),
+// 64 units per workgroup; the first thread of a unit classifies it.
 __global__ __launch_bounds__(256) void k_fwd_plan(ImageView v0, int units, int total, int* fplan) {
   __shared__ int cnt[kPlanBuckets], base[kPlanBuckets];
-  const int id = blockIdx.x * 256 + threadIdx.x;
+  const int id = blockIdx.x * 64 + (threadIdx.x >> 2), sb = threadIdx.x & 3;
   if (threadIdx.x < kPlanBuckets) cnt[threadIdx.x] = 0;
   __syncthreads();
-  int cls[2] = {-1, -1}, rank[2] = {0, 0}, item[2] = {0, 0};
+  int mine = 0;
   if (id < total) {
     const int b = id / units;
-    int c[4];
-    dev::unit_candidates(image_of(v0, b), id - b * units, c);
+    mine = dev::block_candidates(image_of(v0, b), id - b * units, sb);
+  }
+  // the unit's four counts in every one of its threads (id is the same for
+  // the four lanes, so all four take part in the shuffles)
+  int c[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) c[k] = __shfl(mine, (threadIdx.x & 63 & ~3) + k);
+  int cls[2] = {-1, -1}, rank[2] = {0, 0}, item[2] = {0, 0};
+  if (id < total && sb == 0) {
     const int sum = c[0] + c[1] + c[2] + c[3];
     if (dev::unit_is_heavy(c)) {
       cls[0] = cost_class(c[0] + c[1]);
@@ -170,7 +179,7 @@ hipError_t launch_forward_t(const Geometry& g, const ImageView& v0, int* fplan, 
     const int total = g.fwd_units * g.B;  // checked against 2^31 / kPlanBuckets
     {
       ProfRange pr_("fwd_plan", st);
-      hipLaunchKernelGGL(k_fwd_plan, dim3(cdiv(total, 256)), dim3(256), 0, st, v0, g.fwd_units,
+      hipLaunchKernelGGL(k_fwd_plan, dim3(cdiv(total, 64)), dim3(256), 0, st, v0, g.fwd_units,
                          total, fplan);
     }
     ProfRange pr_("forward", st);
