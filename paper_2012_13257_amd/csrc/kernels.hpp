@@ -247,6 +247,10 @@ __host__ __device__ constexpr int radix_scatter_lds_ints() { return 6 * 256 + 4 
 // the tile in LDS (wavefronts in index order, so equal digits keep their
 // input order), which is written out so that every digit's entries form one
 // contiguous run in the output.
+// kWide: the records carry more than four values (CS > 4); those are moved
+// after the first four, all loads of an entry before its stores.  The
+// narrow instantiation (CS = 4) keeps the register budget of the common case.
+template <bool kWide = false>
 __device__ inline void radix_scatter(const ImageView& v, int p, int tile, int* lds) {
   int* wrun = lds;                 // [4][256]
   int* base = lds + 1024;          // [256]
@@ -370,17 +374,22 @@ __device__ inline void radix_scatter(const ImageView& v, int p, int tile, int* l
       }
     }
   }
-  if (v.CS > 4) {  // values beyond the first four
-#pragma unroll
+  if constexpr (kWide) {  // values beyond the first four (CS <= 32: at most 7 more float4s)
+    constexpr int kExtra = 7;
     for (int r = 0; r < kRadixItems; ++r) {
       const int e = t + r * 256;
       if (e >= tn) continue;
       const int src = t0 + ssrc[e];
-      float4* dst = reinterpret_cast<float4*>(cout + (size_t)epos[r] * v.CS);
-      for (int c = 4; c < v.CS; c += 4) {
-        dst[c / 4] = first ? point_values4(v, src, c)
-                           : reinterpret_cast<const float4*>(cin + (size_t)src * v.CS)[c / 4];
+      const float4* rin = reinterpret_cast<const float4*>(cin + (size_t)src * v.CS);
+      float4 x[kExtra];
+#pragma unroll
+      for (int q = 0; q < kExtra; ++q) {
+        if (4 * (q + 1) < v.CS) x[q] = first ? point_values4(v, src, 4 * (q + 1)) : rin[q + 1];
       }
+      float4* dst = reinterpret_cast<float4*>(cout + (size_t)epos[r] * v.CS);
+#pragma unroll
+      for (int q = 0; q < kExtra; ++q)
+        if (4 * (q + 1) < v.CS) dst[q + 1] = x[q];
     }
   }
   __syncthreads();

@@ -36,11 +36,12 @@ __global__ __launch_bounds__(256) void k_radix_scan(ImageView v0, int p) {
   dev::radix_scan_digit(image_of(v0, blockIdx.y), p, blockIdx.x, tmp4);
 }
 
+template <bool kWide>
 __global__ __launch_bounds__(256) void k_radix_scatter(ImageView v0, int p, int per8) {
   __shared__ int lds[dev::radix_scatter_lds_ints()];
   const int tile = xcd_tile(per8);
   if (tile >= v0.ntiles) return;
-  dev::radix_scatter(image_of(v0, blockIdx.y), p, tile, lds);
+  dev::radix_scatter<kWide>(image_of(v0, blockIdx.y), p, tile, lds);
 }
 
 // also clears the counters of the forward's work order (fplan, 64 ints)
@@ -234,7 +235,12 @@ hipError_t launch_forward_all(const Geometry& g, const ImageView& v0, int* fplan
     }
     {
       ProfRange pr_("radix_scatter", st);
-      hipLaunchKernelGGL(k_radix_scatter, dim3(8 * per8, g.B), dim3(256), 0, st, v0, p, per8);
+      if (g.CS > 4)
+        hipLaunchKernelGGL(k_radix_scatter<true>, dim3(8 * per8, g.B), dim3(256), 0, st, v0, p,
+                           per8);
+      else
+        hipLaunchKernelGGL(k_radix_scatter<false>, dim3(8 * per8, g.B), dim3(256), 0, st, v0, p,
+                           per8);
     }
   }
   {
