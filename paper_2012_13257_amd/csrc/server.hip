@@ -206,6 +206,10 @@ class GpuExecutor {
       e = hipGraphInstantiate(&x.exec, graph, nullptr, nullptr, 0);
       hipGraphDestroy(graph);
       if (e != hipSuccess) return fail_hip(e, "hipGraphInstantiate");
+      // one replay over the empty table (every phase has zero units), so the
+      // first batch of each context does not pay the graph's first-launch cost
+      if ((e = hipGraphLaunch(x.exec, x.stream)) != hipSuccess) return fail_hip(e, "hipGraphLaunch");
+      if ((e = hipStreamSynchronize(x.stream)) != hipSuccess) return fail_hip(e, "warm-up replay");
     }
     return INTERP_OK;
   }
