@@ -60,6 +60,24 @@ def test_backward_cfg3_sampled_points():
     check_grad(gs[0, pts], ref["grad_sigma"], ref["scale_sigma"], "cfg3 sigma")
 
 
+def test_backward_cfg5_sampled_points():
+    # 2 x 4096x4096, C=16, sigma up to 3: points of the second image (the batch
+    # offset), at random and the four with the largest disks, against the
+    # oracle's per-point brute force
+    wl = synth.config5()
+    say("backward cfg5 sampled")
+    G = wl.grad_out()
+    gp, gs, gv = _gpu_grads(wl, G)
+    rng = np.random.default_rng(78)
+    pts = np.unique(np.concatenate([rng.choice(wl.N, 12, replace=False),
+                                    np.argsort(wl.sigma[1])[-4:]]))
+    ref = oracle.backward_points(wl.pos, wl.sigma, wl.values, G, wl.H, wl.W, wl.radius, 1, pts,
+                                 workers=oracle.default_workers(), block=1)
+    check_grad(gp[1, pts], ref["grad_pos"], ref["scale_pos"], "cfg5 pos")
+    check_grad(gv[1, pts], ref["grad_values"], ref["scale_values"], "cfg5 values")
+    check_grad(gs[1, pts], ref["grad_sigma"], ref["scale_sigma"], "cfg5 sigma")
+
+
 def test_backward_partition_of_unity_cfg3():
     """sum_j dL/dc_jk equals the sum of G over pixels with Z > 0 (any size)."""
     import torch
