@@ -6,9 +6,10 @@
 // over the flattened work units of all jobs of the batch, finds the job of a
 // unit by binary search and calls the same device function as the
 // single-call path, so every request computes exactly the bits it would
-// compute alone.  The phase sequence (binning, forward, backward) is captured
-// once per batch context into a HIP graph; a batch is one table upload plus
-// one graph replay on the context's stream.  Per-job state lives in one
+// compute alone.  The phase sequences (binning with 1-3 radix passes, forward,
+// with or without the backward) are captured once per batch context into HIP
+// graphs; a batch is one table upload plus one replay, on the context's
+// stream, of the graph that covers its jobs.  Per-job state lives in one
 // device arena allocated at creation (the HBM budget).
 //
 // Host side: the Scheduler (scheduler.hpp) admits requests by free slots and
@@ -33,7 +34,7 @@ constexpr int kContexts = 4;       // concurrent batches
 constexpr int kGrid = 1024;        // workgroups of every job-table kernel
 static_assert(kGrid % 8 == 0, "the job-table kernels deal units to the eight XCDs");
 constexpr int kServeMaxC = 4;      // channels per request on the serving path
-constexpr int kServePasses = 3;    // radix passes the captured graph covers
+constexpr int kServePasses = 3;    // radix passes the captured graphs cover
 
 enum Phase {
   PH_KEYS = 0,
@@ -148,6 +149,32 @@ void enqueue_phase(const JobTable* dtab, hipStream_t st) {
   hipLaunchKernelGGL(kj_phase<PH>, dim3(kGrid), dim3(256), 0, st, dtab);
 }
 
+// The phase sequence of a batch whose jobs need at most np radix passes
+// (1..3; a job with none is covered too) and, if bwd, a backward.  The first
+// pass's histogram comes from the key phase, so there is no PH_HIST0.
+void enqueue_phases(const JobTable* dtab, hipStream_t st, int np, bool bwd) {
+  enqueue_phase<PH_KEYS>(dtab, st);
+  enqueue_phase<PH_SCAN0>(dtab, st);
+  enqueue_phase<PH_SCAT0>(dtab, st);
+  if (np >= 2) {
+    enqueue_phase<PH_HIST1>(dtab, st);
+    enqueue_phase<PH_SCAN1>(dtab, st);
+    enqueue_phase<PH_SCAT1>(dtab, st);
+  }
+  if (np >= 3) {
+    enqueue_phase<PH_HIST2>(dtab, st);
+    enqueue_phase<PH_SCAN2>(dtab, st);
+    enqueue_phase<PH_SCAT2>(dtab, st);
+  }
+  enqueue_phase<PH_FINISH>(dtab, st);
+  enqueue_phase<PH_FWD>(dtab, st);
+  if (bwd) {
+    enqueue_phase<PH_BPIX>(dtab, st);
+    enqueue_phase<PH_BPOINT>(dtab, st);
+    enqueue_phase<PH_BSIG>(dtab, st);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // GPU executor
 // ---------------------------------------------------------------------------
@@ -183,33 +210,27 @@ class GpuExecutor {
       // an empty table so that the capture below reads defined memory
       if ((e = hipMemcpy(x.dtab, x.htab, sizeof(JobTable), hipMemcpyHostToDevice)) != hipSuccess)
         return fail_hip(e, "hipMemcpy(table)");
-      // capture the phase sequence once; every batch replays it
-      if ((e = hipStreamBeginCapture(x.stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
-        return fail_hip(e, "hipStreamBeginCapture");
-      enqueue_phase<PH_KEYS>(x.dtab, x.stream);
-      enqueue_phase<PH_SCAN0>(x.dtab, x.stream);
-      enqueue_phase<PH_SCAT0>(x.dtab, x.stream);
-      enqueue_phase<PH_HIST1>(x.dtab, x.stream);
-      enqueue_phase<PH_SCAN1>(x.dtab, x.stream);
-      enqueue_phase<PH_SCAT1>(x.dtab, x.stream);
-      enqueue_phase<PH_HIST2>(x.dtab, x.stream);
-      enqueue_phase<PH_SCAN2>(x.dtab, x.stream);
-      enqueue_phase<PH_SCAT2>(x.dtab, x.stream);
-      enqueue_phase<PH_FINISH>(x.dtab, x.stream);
-      enqueue_phase<PH_FWD>(x.dtab, x.stream);
-      enqueue_phase<PH_BPIX>(x.dtab, x.stream);
-      enqueue_phase<PH_BPOINT>(x.dtab, x.stream);
-      enqueue_phase<PH_BSIG>(x.dtab, x.stream);
-      hipGraph_t graph = nullptr;
-      e = hipStreamEndCapture(x.stream, &graph);
-      if (e != hipSuccess) return fail_hip(e, "hipStreamEndCapture");
-      e = hipGraphInstantiate(&x.exec, graph, nullptr, nullptr, 0);
-      hipGraphDestroy(graph);
-      if (e != hipSuccess) return fail_hip(e, "hipGraphInstantiate");
-      // one replay over the empty table (every phase has zero units), so the
-      // first batch of each context does not pay the graph's first-launch cost
-      if ((e = hipGraphLaunch(x.exec, x.stream)) != hipSuccess) return fail_hip(e, "hipGraphLaunch");
-      if ((e = hipStreamSynchronize(x.stream)) != hipSuccess) return fail_hip(e, "warm-up replay");
+      // one graph per (radix passes, backward) combination, captured once;
+      // a batch replays the one that covers the most passes and the backward
+      // of its jobs, so it does not launch phases that have no work
+      for (int np = 1; np <= kServePasses; ++np) {
+        for (int bwd = 0; bwd < 2; ++bwd) {
+          if ((e = hipStreamBeginCapture(x.stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return fail_hip(e, "hipStreamBeginCapture");
+          enqueue_phases(x.dtab, x.stream, np, bwd != 0);
+          hipGraph_t graph = nullptr;
+          e = hipStreamEndCapture(x.stream, &graph);
+          if (e != hipSuccess) return fail_hip(e, "hipStreamEndCapture");
+          hipGraphExec_t& ge = x.exec[np - 1][bwd];
+          e = hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0);
+          hipGraphDestroy(graph);
+          if (e != hipSuccess) return fail_hip(e, "hipGraphInstantiate");
+          // one replay over the empty table (every phase has zero units), so
+          // the first batch that uses the graph does not pay its first-launch cost
+          if ((e = hipGraphLaunch(ge, x.stream)) != hipSuccess) return fail_hip(e, "hipGraphLaunch");
+          if ((e = hipStreamSynchronize(x.stream)) != hipSuccess) return fail_hip(e, "warm-up replay");
+        }
+      }
     }
     return INTERP_OK;
   }
@@ -219,7 +240,9 @@ class GpuExecutor {
     for (int c = 0; c < kContexts; ++c) {
       Ctx& x = ctx_[c];
       if (x.stream) hipStreamSynchronize(x.stream);
-      if (x.exec) hipGraphExecDestroy(x.exec);
+      for (auto& row : x.exec)
+        for (hipGraphExec_t ge : row)
+          if (ge) hipGraphExecDestroy(ge);
       if (x.done) hipEventDestroy(x.done);
       if (x.stream) hipStreamDestroy(x.stream);
       if (x.htab) hipHostFree(x.htab);
@@ -237,6 +260,8 @@ class GpuExecutor {
     JobTable* T = x.htab;
     const int nj = (int)jobs.size();
     T->njobs = nj;
+    int need_passes = 1;
+    bool need_bwd = false;
     for (int ph = 0; ph < PH_COUNT; ++ph) T->units[ph][0] = 0;
     for (int i = 0; i < nj; ++i) {
       const Request& rq = jobs[i]->req;
@@ -249,6 +274,8 @@ class GpuExecutor {
                              r.grad_out ? r.grad_values : nullptr);
       T->ct[i] = g.CT;
       const bool bwd = r.grad_out != nullptr;
+      need_bwd = need_bwd || bwd;
+      need_passes = std::max(need_passes, g.N > 0 ? g.npass : 0);
       int u[PH_COUNT] = {};
       u[PH_KEYS] = g.N > 0 ? g.ntiles : 0;
       for (int p = 0; p < kServePasses; ++p) {
@@ -268,7 +295,7 @@ class GpuExecutor {
     const size_t bytes = offsetof(JobTable, view) + sizeof(ImageView) * (size_t)nj;
     hipError_t e = hipMemcpyAsync(x.dtab, T, bytes, hipMemcpyHostToDevice, x.stream);
     if (e != hipSuccess) return fail_hip(e, "hipMemcpyAsync(table)");
-    e = hipGraphLaunch(x.exec, x.stream);
+    e = hipGraphLaunch(x.exec[need_passes - 1][need_bwd ? 1 : 0], x.stream);
     if (e != hipSuccess) return fail_hip(e, "hipGraphLaunch");
     e = hipEventRecord(x.done, x.stream);
     if (e != hipSuccess) return fail_hip(e, "hipEventRecord");
@@ -291,7 +318,7 @@ class GpuExecutor {
     JobTable* htab = nullptr;
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipGraphExec_t exec[kServePasses][2] = {};  // [radix passes - 1][backward]
   };
   int device_ = 0;
   void* arena_ = nullptr;
