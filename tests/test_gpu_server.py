@@ -132,3 +132,40 @@ def test_server_many_requests_small_budget_completes():
         assert srv.drain(120000)
         for t in ts:
             assert srv.result(t)["state"] == 2
+
+
+def test_server_three_pass_request_alone_and_in_mix():
+    """A 2056 x 2056 request has 257 x 257 bins (17 key bits): its batch replays
+    the graph with three radix passes; with and without the backward, alone and
+    next to small requests, its bits equal the single-call path's."""
+    import torch
+    from paper_2012_13257_amd.server import Server
+    big = synth.random_workload(4713, 1, 30000, 2056, 2056, C=3, sigma=1.1, blob_frac=0.5,
+                                blob_std=(20.0, 80.0))
+    small = _requests(6, 55, sides=(32, 64))
+    pb, sb, vb, Gb = _dev(big)
+    dev = [_dev(wl) for _, wl in small]
+    torch.cuda.synchronize()
+    ref_f = _single(pb, sb, vb, Gb, big, False)
+    ref_b = _single(pb, sb, vb, Gb, big, True)
+    ref_s = [_single(p, s, v, G, wl, r.backward) for (r, wl), (p, s, v, G) in zip(small, dev)]
+    torch.cuda.synchronize()
+    say("server three-pass request", big.H, big.W, big.N)
+    with Server(budget_bytes=2 << 30, max_slots=16) as srv:
+        for G, ref in ((None, ref_f), (Gb, ref_b)):
+            t = srv.submit(pb, sb, vb, big.H, big.W, big.radius, grad_out=G)
+            assert srv.drain(60000)
+            res = srv.result(t)
+            assert res["state"] == 2, res
+            for key, val in ref.items():
+                assert torch.equal(res[key], val), ("alone", key)
+        tickets = [srv.submit(pb, sb, vb, big.H, big.W, big.radius, grad_out=Gb)]
+        for (r, wl), (p, s, v, G) in zip(small, dev):
+            tickets.append(srv.submit(p, s, v, wl.H, wl.W, wl.radius,
+                                      grad_out=G if r.backward else None))
+        assert srv.drain(60000)
+        for k, (t, ref) in enumerate(zip(tickets, [ref_b] + ref_s)):
+            res = srv.result(t)
+            assert res["state"] == 2, (k, res)
+            for key, val in ref.items():
+                assert torch.equal(res[key], val), ("mix", k, key)
