@@ -31,8 +31,6 @@ namespace serve {
 
 constexpr int kMaxJobs = 256;      // jobs per batch (table capacity)
 constexpr int kContexts = 4;       // concurrent batches
-constexpr int kGrid = 1024;        // workgroups of every job-table kernel
-static_assert(kGrid % 8 == 0, "the job-table kernels deal units to the eight XCDs");
 constexpr int kServeMaxC = 4;      // channels per request on the serving path
 constexpr int kServePasses = 3;    // radix passes the captured graphs cover
 
@@ -44,6 +42,14 @@ enum Phase {
   PH_FINISH, PH_FWD, PH_BPIX, PH_BPOINT, PH_BSIG,
   PH_COUNT
 };
+
+// Workgroups per compute unit of each job-table kernel: as many as its LDS
+// lets one compute unit hold (forward lists 32 KB: 5; adjoint window 37 KB:
+// 4; the others 8), so a phase fills the chip once and then strides.
+template <int PH>
+constexpr int phase_wgs_per_cu() {
+  return PH == PH_FWD ? 5 : PH == PH_BPOINT ? 4 : 8;
+}
 
 struct JobTable {
   int njobs;
@@ -144,34 +150,37 @@ __global__ __launch_bounds__(256) void kj_phase(const JobTable* __restrict__ T) 
   }
 }
 
+// cus: compute units of the device; the grid is a multiple of 8 (the
+// radix phases deal their tiles to the eight XCDs)
 template <int PH>
-void enqueue_phase(const JobTable* dtab, hipStream_t st) {
-  hipLaunchKernelGGL(kj_phase<PH>, dim3(kGrid), dim3(256), 0, st, dtab);
+void enqueue_phase(const JobTable* dtab, hipStream_t st, int cus) {
+  const int grid = (phase_wgs_per_cu<PH>() * cus + 7) / 8 * 8;
+  hipLaunchKernelGGL(kj_phase<PH>, dim3(grid), dim3(256), 0, st, dtab);
 }
 
 // The phase sequence of a batch whose jobs need at most np radix passes
 // (1..3; a job with none is covered too) and, if bwd, a backward.  The first
 // pass's histogram comes from the key phase, so there is no PH_HIST0.
-void enqueue_phases(const JobTable* dtab, hipStream_t st, int np, bool bwd) {
-  enqueue_phase<PH_KEYS>(dtab, st);
-  enqueue_phase<PH_SCAN0>(dtab, st);
-  enqueue_phase<PH_SCAT0>(dtab, st);
+void enqueue_phases(const JobTable* dtab, hipStream_t st, int cus, int np, bool bwd) {
+  enqueue_phase<PH_KEYS>(dtab, st, cus);
+  enqueue_phase<PH_SCAN0>(dtab, st, cus);
+  enqueue_phase<PH_SCAT0>(dtab, st, cus);
   if (np >= 2) {
-    enqueue_phase<PH_HIST1>(dtab, st);
-    enqueue_phase<PH_SCAN1>(dtab, st);
-    enqueue_phase<PH_SCAT1>(dtab, st);
+    enqueue_phase<PH_HIST1>(dtab, st, cus);
+    enqueue_phase<PH_SCAN1>(dtab, st, cus);
+    enqueue_phase<PH_SCAT1>(dtab, st, cus);
   }
   if (np >= 3) {
-    enqueue_phase<PH_HIST2>(dtab, st);
-    enqueue_phase<PH_SCAN2>(dtab, st);
-    enqueue_phase<PH_SCAT2>(dtab, st);
+    enqueue_phase<PH_HIST2>(dtab, st, cus);
+    enqueue_phase<PH_SCAN2>(dtab, st, cus);
+    enqueue_phase<PH_SCAT2>(dtab, st, cus);
   }
-  enqueue_phase<PH_FINISH>(dtab, st);
-  enqueue_phase<PH_FWD>(dtab, st);
+  enqueue_phase<PH_FINISH>(dtab, st, cus);
+  enqueue_phase<PH_FWD>(dtab, st, cus);
   if (bwd) {
-    enqueue_phase<PH_BPIX>(dtab, st);
-    enqueue_phase<PH_BPOINT>(dtab, st);
-    enqueue_phase<PH_BSIG>(dtab, st);
+    enqueue_phase<PH_BPIX>(dtab, st, cus);
+    enqueue_phase<PH_BPOINT>(dtab, st, cus);
+    enqueue_phase<PH_BSIG>(dtab, st, cus);
   }
 }
 
@@ -194,6 +203,9 @@ class GpuExecutor {
     device_ = device;
     hipError_t e = hipSetDevice(device);
     if (e != hipSuccess) return fail_hip(e, "hipSetDevice");
+    int cus = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    if (e != hipSuccess || cus <= 0) return fail_hip(e, "hipDeviceGetAttribute(compute units)");
     if (budget) {
       e = hipMalloc(&arena_, budget);
       if (e != hipSuccess) return fail_hip(e, "hipMalloc(arena)");
@@ -217,7 +229,7 @@ class GpuExecutor {
         for (int bwd = 0; bwd < 2; ++bwd) {
           if ((e = hipStreamBeginCapture(x.stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
             return fail_hip(e, "hipStreamBeginCapture");
-          enqueue_phases(x.dtab, x.stream, np, bwd != 0);
+          enqueue_phases(x.dtab, x.stream, cus, np, bwd != 0);
           hipGraph_t graph = nullptr;
           e = hipStreamEndCapture(x.stream, &graph);
           if (e != hipSuccess) return fail_hip(e, "hipStreamEndCapture");
