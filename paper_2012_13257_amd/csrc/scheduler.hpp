@@ -190,16 +190,29 @@ class Scheduler {
     --outstanding_;
   }
 
-  // One scheduling round; returns true if a batch is in flight.
-  bool round() {
+  // One scheduling round; returns true if a batch is in flight.  Entered and
+  // left with the lock held, which is released around every executor call
+  // (event queries, table uploads, graph launches can take a while and must
+  // not hold up submit / poll).  Only this thread touches the contexts, the
+  // pending list and the arena; a job's request and arena range do not change
+  // while it runs, and poll never frees a running job.
+  bool round(std::unique_lock<std::mutex>& lk) {
     // 1. retire finished batches
-    for (size_t c = 0; c < ctx_busy_.size(); ++c) {
-      if (!ctx_busy_[c]) continue;
-      const int q = ex_->query((int)c);
-      if (q == 0) continue;
-      for (J* j : ctx_jobs_[c]) finish(j, q > 0 ? INTERP_DONE : INTERP_FAILED, q > 0 ? INTERP_OK : q);
-      ctx_jobs_[c].clear();
-      ctx_busy_[c] = false;
+    std::vector<int> busy, status;
+    for (size_t c = 0; c < ctx_busy_.size(); ++c)
+      if (ctx_busy_[c]) busy.push_back((int)c);
+    if (!busy.empty()) {
+      status.resize(busy.size());
+      lk.unlock();
+      for (size_t k = 0; k < busy.size(); ++k) status[k] = ex_->query(busy[k]);
+      lk.lock();
+      for (size_t k = 0; k < busy.size(); ++k) {
+        const int c = busy[k], q = status[k];
+        if (q == 0) continue;
+        for (J* j : ctx_jobs_[c]) finish(j, q > 0 ? INTERP_DONE : INTERP_FAILED, q > 0 ? INTERP_OK : q);
+        ctx_jobs_[c].clear();
+        ctx_busy_[c] = false;
+      }
     }
     // 2. admit in arrival order while a slot and arena space are free
     while (!queue_.empty() && slots_used_ < max_slots_) {
@@ -215,40 +228,51 @@ class Scheduler {
     }
     if (arena_.used() > peak_arena_) peak_arena_ = arena_.used();
     if (slots_used_ > peak_slots_) peak_slots_ = slots_used_;
-    // 3. launch the admitted jobs as one batch on a free context
+    // 3. launch the admitted jobs as batches on free contexts
+    std::vector<int> go;
     while (!pending_.empty()) {
       int c = -1;
       for (size_t k = 0; k < ctx_busy_.size(); ++k)
         if (!ctx_busy_[k]) { c = (int)k; break; }
       if (c < 0) break;
       const size_t n = std::min(pending_.size(), (size_t)ex_->max_batch());
-      std::vector<J*> batch(pending_.begin(), pending_.begin() + n);
+      ctx_jobs_[c].assign(pending_.begin(), pending_.begin() + n);
       pending_.erase(pending_.begin(), pending_.begin() + n);
-      const int rc = ex_->launch(c, batch);
-      if (rc != INTERP_OK) {
-        for (J* j : batch) finish(j, INTERP_FAILED, rc);
-        continue;
-      }
-      ctx_jobs_[c] = std::move(batch);
       ctx_busy_[c] = true;
-      ++batches_;
+      go.push_back(c);
     }
-    int busy = 0;
-    for (bool b : ctx_busy_) busy += b;
-    if (busy > peak_ctx_) peak_ctx_ = busy;
-    return busy > 0;
+    if (!go.empty()) {
+      std::vector<int> rc(go.size());
+      lk.unlock();
+      for (size_t k = 0; k < go.size(); ++k) rc[k] = ex_->launch(go[k], ctx_jobs_[go[k]]);
+      lk.lock();
+      for (size_t k = 0; k < go.size(); ++k) {
+        const int c = go[k];
+        if (rc[k] == INTERP_OK) {
+          ++batches_;
+          continue;
+        }
+        for (J* j : ctx_jobs_[c]) finish(j, INTERP_FAILED, rc[k]);
+        ctx_jobs_[c].clear();
+        ctx_busy_[c] = false;
+      }
+    }
+    int nbusy = 0;
+    for (bool b : ctx_busy_) nbusy += b;
+    if (nbusy > peak_ctx_) peak_ctx_ = nbusy;
+    return nbusy > 0;
   }
 
   void loop() {
     ex_->thread_init();
     std::unique_lock<std::mutex> lk(mu_);
     while (true) {
-      const bool busy = round();
+      const bool busy = round(lk);
       if (outstanding_ == 0) done_cv_.notify_all();
       if (stop_) break;
       if (busy) {
         // a batch is on the device: poll again shortly, waking up early for arrivals
-        cv_.wait_for(lk, std::chrono::microseconds(20));
+        cv_.wait_for(lk, std::chrono::microseconds(5));
       } else {
         cv_.wait_for(lk, std::chrono::milliseconds(2),
                      [this] { return stop_ || !queue_.empty() || !pending_.empty(); });
@@ -265,8 +289,8 @@ class Scheduler {
       if (!ctx_busy_[c]) continue;
       lk.unlock();
       ex_->wait((int)c);
-      lk.lock();
       const int q = ex_->query((int)c);
+      lk.lock();
       for (J* j : ctx_jobs_[c]) finish(j, q > 0 ? INTERP_DONE : INTERP_FAILED, q > 0 ? INTERP_OK : q);
       ctx_jobs_[c].clear();
       ctx_busy_[c] = false;
