@@ -652,13 +652,6 @@ __device__ inline void forward_block_q(const ImageView& v, int unit, int mode, f
       s_r = o[bx_lo];
       len = o[bx_hi + 1] - s_r;
     }
-    int incl = len;  // inclusive scan of the row lengths over the lanes
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int y = __shfl_up(incl, o);
-      if (lane >= o) incl += y;
-    }
-    (void)incl;
     // Chunk cursor (wave-uniform): row r of the group, offset c in it, the
     // row's first record rs and length rn.  Chunks are 64 records of one row;
     // when two wavefronts share the block they take alternate chunks.
