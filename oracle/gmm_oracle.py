@@ -58,7 +58,7 @@ import numpy as np
 
 __all__ = [
     "predicate", "weights", "forward_pixels", "forward", "backward_points", "backward",
-    "bins", "pair_count",
+    "bins", "pair_count", "reach", "halo_bins",
 ]
 
 
@@ -360,6 +360,37 @@ def backward(pos, sigma, values, G, H: int, W: int, radius: Optional[float],
 # --------------------------------------------------------------------------
 # Spatial bins (the counting sort the GPU path uses to find near points)
 # --------------------------------------------------------------------------
+
+def reach(sigma, radius: float, N: int) -> np.ndarray:
+    """Per-image largest truncation radius max_j f32(radius * sigma_j) (float32).
+
+    sigma is [B, N] (per point) or [B] (shared).  An image without points has
+    reach 0.  This is the distance beyond which no point of the image has
+    weight (the truncation sentence after Eq. 2), so it bounds the bins a
+    pixel must look at.
+    """
+    sigma = np.asarray(sigma, np.float32)
+    B = sigma.shape[0]
+    out = np.zeros(B, np.float32)
+    for b in range(B):
+        if N == 0:
+            continue
+        s = sigma[b] if sigma.ndim == 2 else sigma[b:b + 1]
+        out[b] = np.max((np.float32(radius) * s).astype(np.float32))
+    return out
+
+
+def halo_bins(sigma, radius: float, N: int, tile: int) -> np.ndarray:
+    """Bins of halo K per image: floor((reach + 2^-10) / tile) + 1.
+
+    Every point with weight at a pixel lies in a bin at most K bins away (in x
+    and in y) from the pixel's own bin: |x - u| <= reach, so the bin columns
+    differ by at most ceil(reach / tile) <= K, with the 2^-10 margin covering
+    the float32 rounding of the radius test.
+    """
+    r = reach(sigma, radius, N).astype(np.float64)
+    return (np.floor((r + 2.0 ** -10) / tile) + 1).astype(np.int64)
+
 
 def bins(pos, H: int, W: int, tile: int) -> Dict[str, np.ndarray]:
     """Bin of every point and the stable counting-sort order, per image.

@@ -409,3 +409,147 @@ def test_bins_random_stable_grouped():
         for k in range(0, r["count"].shape[1], 7):
             seg = perm[r["offset"][b, k]: r["offset"][b, k + 1]]
             assert np.all(r["bin_of"][b][seg] == k)
+
+
+# --------------------------------------------------------------------------
+# Tolerance scales (S of the forward; scale_pos / scale_sigma / scale_values
+# of the backward).  Every GPU check divides by them, so each is tied to the
+# pinned outputs and gradients: a scale too large, or missing a factor, fails
+# one of these.
+# --------------------------------------------------------------------------
+
+def test_forward_scale_equals_output_for_nonnegative_values_and_abs_for_constant_negative():
+    """S_ik = sum_j w |c_jk| / Z_i: with every value >= 0 it is the output
+    itself; with one negative constant colour it is that colour's magnitude;
+    it is unchanged when the values change sign and never below |out|."""
+    wl = synth.random_workload(61, 1, 90, 17, 19, C=3, sigma=(0.3, 1.2))
+    r = oracle.forward(wl.pos, wl.sigma, wl.values, wl.H, wl.W, 3.0)
+    m = r["Z"][0] > 0
+    assert m.sum() > 150 and (~m).sum() > 0
+    np.testing.assert_array_equal(r["S"], r["out"])
+    neg = np.full_like(wl.values, -0.625)
+    rn = oracle.forward(wl.pos, wl.sigma, neg, wl.H, wl.W, 3.0)
+    np.testing.assert_allclose(rn["S"][0][:, m], 0.625, rtol=1e-14)
+    assert np.all(rn["S"][0][:, ~m] == 0)
+    mixed = synth.random_workload(62, 1, 90, 17, 19, C=2, sigma=(0.3, 1.2), values="normal")
+    r1 = oracle.forward(mixed.pos, mixed.sigma, mixed.values, 17, 19, 3.0)
+    r2 = oracle.forward(mixed.pos, mixed.sigma, -mixed.values, 17, 19, 3.0)
+    np.testing.assert_array_equal(r1["S"], r2["S"])
+    np.testing.assert_array_equal(r1["out"], -r2["out"])
+    m1 = r1["Z"][0] > 0
+    assert np.all(r1["S"] >= np.abs(r1["out"]))
+    assert np.mean(r1["S"][0][:, m1] > np.abs(r1["out"][0][:, m1]) * (1 + 1e-9)) > 0.5
+
+
+def _one_signed_point_case(per_point: bool):
+    """Point 0 sits above and to the left of the whole image (x, y < 0) and
+    carries the largest value; every other point lies inside with smaller
+    values; G = 1.  Then for point 0 every term of every gradient has one
+    sign: u - x > 0, v - y > 0, d2 > 0, w alpha G > 0 and
+    A = alpha sum_k G (c_0k - o_ik) > 0 (o_i is a weighted mean of values
+    below c_0 wherever another point contributes)."""
+    rng = np.random.default_rng(71)
+    H, W, N = 9, 11, 40
+    pos = np.concatenate([[[-0.75, -1.25]], rng.random((N - 1, 2)) * [W - 1, H - 1]])[None]
+    sig = np.full((1,), 1.4) if not per_point else np.concatenate(
+        [[2.1], rng.uniform(0.6, 1.6, N - 1)])[None]
+    val = np.concatenate([[[5.0]], rng.random((N - 1, 1))])[None]
+    G = np.ones((1, 1, H, W))
+    return pos, sig, val, G, H, W
+
+
+@pytest.mark.parametrize("per_point", [True, False])
+def test_gradient_scales_equal_abs_gradient_when_terms_share_a_sign(per_point):
+    pos, sig, val, G, H, W = _one_signed_point_case(per_point)
+    r = oracle.backward_points(pos, sig, val, G, H, W, 3.0, 0, [0])
+    gp, gs, gv = r["grad_pos"][0], r["grad_sigma"][0], r["grad_values"][0]
+    assert np.all(gp > 1e-3) and gs > 1e-3 and np.all(gv > 1e-3)
+    np.testing.assert_allclose(r["scale_pos"][0], gp, rtol=1e-12)
+    assert r["scale_sigma"][0] == pytest.approx(gs, rel=1e-12)
+    np.testing.assert_allclose(r["scale_values"][0], gv, rtol=1e-12)
+    # the same point's gradients flip sign with G while the scales stay
+    rn = oracle.backward_points(pos, sig, val, -G, H, W, 3.0, 0, [0])
+    np.testing.assert_allclose(rn["grad_pos"][0], -gp, rtol=1e-12)
+    np.testing.assert_allclose(rn["scale_pos"][0], r["scale_pos"][0], rtol=1e-12)
+    assert rn["scale_sigma"][0] == pytest.approx(r["scale_sigma"][0], rel=1e-12)
+    np.testing.assert_allclose(rn["scale_values"][0], r["scale_values"][0], rtol=1e-12)
+
+
+def test_value_gradient_scale_is_a_partition_of_abs_upstream_gradient():
+    """sum_j scale_values_jk = sum over pixels with Z > 0 of |G_ik| exactly
+    (the normalised weights w_ij alpha_i of a pixel sum to one); with G >= 0
+    the scale equals the gradient itself."""
+    wl = synth.random_workload(73, 1, 45, 13, 14, C=3, sigma=(0.3, 1.0))
+    G = wl.grad_out().astype(np.float64)
+    g = oracle.backward(wl.pos, wl.sigma, wl.values, G, wl.H, wl.W, 3.0)
+    m = g["fwd"]["Z"][0] > 0
+    assert (~m).sum() > 0 and np.any(G < 0)
+    lhs = g["scale_values"][0].sum(axis=0)
+    rhs = np.array([np.abs(G[0, k][m]).sum() for k in range(3)])
+    np.testing.assert_allclose(lhs, rhs, rtol=1e-10)
+    ga = oracle.backward(wl.pos, wl.sigma, wl.values, np.abs(G), wl.H, wl.W, 3.0)
+    np.testing.assert_allclose(ga["scale_values"], ga["grad_values"], rtol=1e-12, atol=1e-300)
+    np.testing.assert_allclose(ga["scale_values"], g["scale_values"], rtol=1e-12)
+
+
+def test_gradient_scales_bound_the_gradient_and_scale_with_g():
+    """scale >= |grad| (triangle inequality), strictly for most points when
+    the terms have mixed signs, and every scale is linear in |G|."""
+    wl = synth.random_workload(79, 1, 60, 12, 15, C=2, sigma=(0.5, 1.6), values="normal")
+    G = wl.grad_out().astype(np.float64)
+    g = oracle.backward(wl.pos, wl.sigma, wl.values, G, wl.H, wl.W, 3.0)
+    g3 = oracle.backward(wl.pos, wl.sigma, wl.values, -3.0 * G, wl.H, wl.W, 3.0)
+    for name in ("pos", "sigma", "values"):
+        s, v = g["scale_" + name], g["grad_" + name]
+        assert np.all(s >= np.abs(v) * (1 - 1e-12))
+        assert np.mean(s > np.abs(v) * (1 + 1e-6)) > 0.8
+        np.testing.assert_allclose(g3["scale_" + name], 3.0 * s, rtol=1e-12)
+        np.testing.assert_allclose(g3["grad_" + name], -3.0 * v, rtol=1e-11, atol=1e-14)
+
+
+def test_shared_sigma_scale_is_sum_of_per_point_scales():
+    """For a shared sigma the gradient is the sum over the image's points and
+    its scale the sum of their scales: both equal the per-point results of the
+    same sigma given per point."""
+    wl = synth.random_workload(83, 2, 30, 10, 12, C=2, sigma=0.9)
+    G = wl.grad_out().astype(np.float64)
+    gs = oracle.backward(wl.pos, wl.sigma, wl.values, G, wl.H, wl.W, 3.0)
+    per = np.repeat(wl.sigma[:, None], wl.N, axis=1)
+    gp = oracle.backward(wl.pos, per, wl.values, G, wl.H, wl.W, 3.0)
+    for b in range(2):
+        assert gs["grad_sigma"][b] == pytest.approx(gp["grad_sigma"][b].sum(), rel=1e-12)
+        assert gs["scale_sigma"][b] == pytest.approx(gp["scale_sigma"][b].sum(), rel=1e-12)
+
+
+def test_reach_and_halo_cover_every_included_pair():
+    """Every pixel-point pair inside the radius (brute force) has the point at
+    most K bins away from the pixel's bin in x and y, and within the reach
+    in pixels; the reach is the largest f32(radius * sigma) exactly."""
+    wl = synth.random_workload(89, 2, 400, 37, 45, C=1, sigma=(0.5, 3.0), blob_frac=0.5,
+                               blob_std=(2.0, 5.0))
+    T = 8
+    K = oracle.halo_bins(wl.sigma, 3.0, wl.N, T)
+    R = oracle.reach(wl.sigma, 3.0, wl.N)
+    for b in range(2):
+        assert R[b] == np.float32(3.0) * wl.sigma[b].max()
+        bins = oracle.bins(wl.pos, wl.H, wl.W, T)
+        nbx = bins["nbx"]
+        key = bins["bin_of"][b]
+        vv, uu = np.meshgrid(np.arange(wl.H), np.arange(wl.W), indexing="ij")
+        inc = oracle.predicate(uu[..., None], vv[..., None], wl.pos[b, :, 0], wl.pos[b, :, 1],
+                               wl.sigma[b], 3.0)
+        v_i, u_i, j_i = np.nonzero(inc)
+        assert j_i.size > 1000
+        assert np.all(np.abs(u_i - wl.pos[b, j_i, 0]) <= R[b])
+        assert np.all(np.abs(v_i - wl.pos[b, j_i, 1]) <= R[b])
+        assert np.all(np.abs(key[j_i] % nbx - u_i // T) <= K[b])
+        assert np.all(np.abs(key[j_i] // nbx - v_i // T) <= K[b])
+    # a point exactly at the reach from the last pixel of a bin sits in the next bin
+    pos = np.array([[[10.0, 2.0]]], np.float32)
+    assert oracle.predicate(7, 2, 10.0, 2.0, np.float32(1.0), 3.0)
+    assert oracle.bins(pos, 16, 16, 8)["bin_of"][0, 0] == 1
+    assert oracle.halo_bins(np.array([1.0], np.float32), 3.0, 1, 8)[0] >= 1
+    assert oracle.halo_bins(np.array([[2.0, 1.0]], np.float32), 4.0, 2, 8)[0] == 2
+    shared = oracle.reach(np.array([0.7, 1.1], np.float32), 3.0, 10)
+    assert list(shared) == [np.float32(3.0) * np.float32(0.7), np.float32(3.0) * np.float32(1.1)]
+    assert list(oracle.reach(np.zeros((1, 0), np.float32), 3.0, 0)) == [0.0]
