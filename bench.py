@@ -30,8 +30,13 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 CU, SIMD_LANES_PER_CU, CLOCK_GHZ = 256, 64, 2.4
 VALU_PEAK_TLANEOPS = CU * SIMD_LANES_PER_CU * CLOCK_GHZ / 1000.0   # 39.32 T lane-ops/s
-# Algorithmic VALU lane-ops per pixel-point pair inside the radius (the exp
-# counts as one: measured, it overlaps fully with the other VALU work):
+# Algorithmic VALU lane-ops per pixel-point pair inside the radius.  The
+# method's count (the roofline's `frac`): forward 8 + C (2 sub, a mul and an
+# FMA for d2, 1 mul by the exponent scale, compare + select, 1 add for Z, C
+# FMAs), backward 13 + 2C, with the one v_exp_f32 per pair and pass counted
+# against its own rate.  The implementation's count (`frac_impl`) follows the
+# float32 radius test, which rounds d2 without contraction (one more op), and
+# counts the exp as a VALU op (measured, it overlaps fully with the rest):
 #   forward  2 sub + 2 mul + 1 add (d2), 1 mul (exponent), 1 exp, 1 cmp,
 #            1 select, 1 add (Z), C FMAs                       = 10 + C
 #   backward 1 sub + 1 mul + 1 add (d2, the row term amortised), 1 cmp,
@@ -68,11 +73,33 @@ def forward_traffic():
 
 
 def fwd_ops(C):
-    return 10 + C
+    """Method count of the forward: VALU lane-ops per in-radius pair."""
+    return 8 + C
 
 
 def bwd_ops(C):
+    """Method count of the adjoint: VALU lane-ops per in-radius pair."""
+    return 13 + 2 * C
+
+
+def fwd_ops_impl(C):
+    return 10 + C
+
+
+def bwd_ops_impl(C):
     return 11 + 2 * C
+
+
+def algorithmic_bytes(B, N, C, H, W, per_point, backward):
+    """HBM bytes the method must move: inputs read once, outputs written once
+    (forward: points, image and Z; backward: G, out and Z read, points read,
+    gradients written)."""
+    pts = B * N * (8 + 4 * per_point + 4 * C)
+    fwd = pts + B * H * W * 4 * C + B * H * W * 4
+    if not backward:
+        return fwd
+    bwd = B * H * W * (8 * C + 4) + pts + B * N * (4 * C + 8 + 4 * per_point)
+    return fwd + bwd
 
 
 def pair_count(pos: np.ndarray, sigma: np.ndarray, H: int, W: int, radius: float) -> int:
@@ -158,6 +185,17 @@ def capture(fn):
     return g
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(wl, G, budget_s: float):
     """The oracle as it stands, on a bounded sample of the same workload."""
     import oracle
@@ -188,7 +226,10 @@ def cpu_baseline(wl, G, budget_s: float):
     t_bwd = (time.perf_counter() - t0) / n_pt
     per_px = t_fwd + t_bwd * (wl.N / (wl.H * wl.W))
     return {"value": 1.0 / per_px / 1e6, "unit": "Mpix/s (fwd+bwd)", "cores": workers,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0)),
+            "threads_note": "oracle thread pool = the CPUs this process may run on, at most 16 "
+                            "(the host share of one GPU)",
             "sample": f"{n_px} random pixels forward + {n_pt} random points backward of the "
                       f"{wl.H}x{wl.W} N={wl.N} workload, extrapolated linearly to the full image "
                       f"(fwd {t_fwd * 1e3:.2f} ms/pixel, bwd {t_bwd * 1e3:.1f} ms/point)",
@@ -212,9 +253,15 @@ def measure_peaks(log):
     src = torch.ones(n4 * 4, device="cuda")
     dst = torch.empty_like(src)
     res = {}
-    for which, name in ((0, "fma"), (1, "exp"), (2, "mix"), (3, "copy")):
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    runs = [(0, 0, "fma"), (1, 0, "exp"), (2, 0, "mix"), (3, 0, "copy")]
+    # streaming copy and read at 4, 8 and 16 workgroups per compute unit (best kept)
+    runs += [(4, k * cus, f"copy_stream{k}") for k in (4, 8, 16)]
+    runs += [(5, k * cus, f"read_stream{k}") for k in (4, 8, 16)]
+    for which, blocks, name in runs:
         def go():
-            v = lib.gmm_peak_launch(which, 0, out.data_ptr(), src.data_ptr(), dst.data_ptr(), n4, st)
+            v = lib.gmm_peak_launch(which, blocks, out.data_ptr(), src.data_ptr(), dst.data_ptr(),
+                                    n4, st)
             if v < 0:
                 raise RuntimeError("peak kernel launch failed")
             return v
@@ -230,11 +277,16 @@ def measure_peaks(log):
         torch.cuda.synchronize()
         sec = a.elapsed_time(b) / 1e3 / reps
         res[name] = work / sec
+    best_copy = max(v for k, v in res.items() if k.startswith("copy"))
+    best_read = max(v for k, v in res.items() if k.startswith("read"))
     peaks = {"valu_fma_tlaneops": round(res["fma"] / 1e12, 2),
              "exp_tlaneops": round(res["exp"] / 1e12, 2),
              "mix_iter_per_ns_per_lane": None,
              "exp_issue_slots": round(res["fma"] / res["exp"], 2),
-             "hbm_copy_gbs": round(res["copy"] / 1e9, 1)}
+             "hbm_copy_gbs": round(best_copy / 1e9, 1),
+             "hbm_read_gbs": round(best_read / 1e9, 1),
+             "hbm_copy_variants_gbs": {k: round(v / 1e9, 1) for k, v in res.items()
+                                       if k.startswith(("copy", "read"))}}
     # mix: 7 VALU instructions per chain-iteration, one of them exp
     mix_inst = res["mix"] * 7
     peaks["mix_tlaneops"] = round(mix_inst / 1e12, 2)
@@ -242,6 +294,104 @@ def measure_peaks(log):
     log(f"measured ceilings: {peaks}")
     del src, dst
     return peaks
+
+
+def measure_workload(wl, steps: int, warmup: int, backward: bool, log):
+    """Times one named workload through the C ABI (eager calls, inputs in HBM):
+    ms per step (forward, + backward when asked), Mpix/s, per-kernel event
+    averages, the exact in-radius pair count, and the fraction of the ALU and
+    HBM ceilings the dominant kernels and the whole step reach."""
+    import ctypes
+    import torch
+    from paper_2012_13257_amd import _lib, interp
+    pos, sig, val = _to_dev(wl)
+    prob = interp.problem(pos, sig, val, wl.H, wl.W, wl.radius)
+    L = _lib.lib()
+    out = torch.empty((wl.B, wl.C, wl.H, wl.W), device="cuda")
+    saved = interp.Saved(prob, pos.device)
+    work = interp.Workspace(prob, pos.device)
+    pb = ctypes.byref(prob)
+    G = gp = gs = gv = None
+    if backward:
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(wl.grad_seed)
+        G = torch.randn((wl.B, wl.C, wl.H, wl.W), generator=gen, device="cuda")
+        gp, gs, gv = torch.empty_like(pos), torch.empty_like(sig), torch.empty_like(val)
+
+    def fwd():
+        st = torch.cuda.current_stream().cuda_stream
+        _lib.check("interp_forward", L.interp_forward(
+            pb, pos.data_ptr(), sig.data_ptr(), val.data_ptr(), out.data_ptr(), saved.addr,
+            saved.nbytes, work.addr, work.nbytes, st))
+
+    def step():
+        fwd()
+        if backward:
+            st = torch.cuda.current_stream().cuda_stream
+            _lib.check("interp_backward", L.interp_backward(
+                pb, pos.data_ptr(), sig.data_ptr(), val.data_ptr(), out.data_ptr(), saved.addr,
+                saved.nbytes, G.data_ptr(), gp.data_ptr(), gs.data_ptr(), gv.data_ptr(), work.addr,
+                work.nbytes, st))
+
+    ms_step, _, _ = time_steps(step, steps, warmup, profile=False)
+    ms_fwd, _, _ = time_steps(fwd, steps, warmup, profile=False)
+    _, _, kernels = time_steps(step, steps, warmup, profile=True)
+    P = pair_count(wl.pos, wl.sigma, wl.H, wl.W, wl.radius)
+    pix = wl.B * wl.H * wl.W
+    res = {"B": wl.B, "H": wl.H, "W": wl.W, "N": wl.N, "C": wl.C, "pairs_in_radius": P,
+           "ms_per_step": round(ms_step, 4), "mpix_s": round(pix / (ms_step * 1e-3) / 1e6, 1),
+           "fwd_ms": round(ms_fwd, 4), "fwd_mpix_s": round(pix / (ms_fwd * 1e-3) / 1e6, 1),
+           "kernels_us": {k: round(v["avg_us"], 2) for k, v in kernels.items()}}
+    # ALU fraction of the two pair kernels (method count), HBM fraction of the
+    # whole step (algorithmic bytes over the step time)
+    for kname, ops in (("forward", fwd_ops(wl.C)), ("bwd_point", bwd_ops(wl.C))):
+        if kname in kernels:
+            a = P * ops / (kernels[kname]["avg_us"] * 1e-6) / 1e12
+            res[kname + "_alu_frac"] = round(a / VALU_PEAK_TLANEOPS, 4)
+    per_point = int(wl.sigma.ndim == 2)
+    nbytes = algorithmic_bytes(wl.B, wl.N, wl.C, wl.H, wl.W, per_point, backward)
+    res["algorithmic_bytes"] = nbytes
+    res["step_hbm_frac"] = round(nbytes / (ms_step * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)
+    # the step's own roofline: the larger of the ALU and HBM times at the peaks
+    t_alu = P * (fwd_ops(wl.C) + (bwd_ops(wl.C) if backward else 0)) / (VALU_PEAK_TLANEOPS * 1e12)
+    t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
+    res["step_roofline_us"] = round(max(t_alu, t_hbm) * 1e6, 2)
+    res["step_bound"] = "alu" if t_alu >= t_hbm else "hbm"
+    res["step_frac"] = round(max(t_alu, t_hbm) / (ms_step * 1e-3), 4)
+    log(f"{wl.name}: {res}")
+    del out, saved, work, G, gp, gs, gv, pos, sig, val
+    torch.cuda.empty_cache()
+    return res
+
+
+def latency_small(wl, steps: int, warmup: int, log):
+    """Forward latency of the small 64x64 workload: one C-ABI call per step,
+    eager and replayed from a HIP graph (the call is launch-bound)."""
+    import ctypes
+    import torch
+    from paper_2012_13257_amd import _lib, interp
+    pos, sig, val = _to_dev(wl)
+    prob = interp.problem(pos, sig, val, wl.H, wl.W, wl.radius)
+    L = _lib.lib()
+    out = torch.empty((wl.B, wl.C, wl.H, wl.W), device="cuda")
+    saved = interp.Saved(prob, pos.device)
+    work = interp.Workspace(prob, pos.device)
+    pb = ctypes.byref(prob)
+
+    def fwd():
+        st = torch.cuda.current_stream().cuda_stream
+        _lib.check("interp_forward", L.interp_forward(
+            pb, pos.data_ptr(), sig.data_ptr(), val.data_ptr(), out.data_ptr(), saved.addr,
+            saved.nbytes, work.addr, work.nbytes, st))
+
+    ms_eager, wall, _ = time_steps(fwd, steps, warmup, profile=False)
+    g = capture(fwd)
+    ms_graph, _, _ = time_steps(g.replay, steps, warmup, profile=False)
+    res = {"B": wl.B, "H": wl.H, "W": wl.W, "N": wl.N, "C": wl.C,
+           "fwd_us_eager": round(ms_eager * 1e3, 2), "fwd_us_graph": round(ms_graph * 1e3, 2),
+           "fwd_us_host_wall": round(wall / steps * 1e6, 2)}
+    log(f"{wl.name}: {res}")
+    return res
 
 
 def serving_benchmark(log, n_requests: int = 4096, seed: int = 1004, budget_gb: float = 24.0,
@@ -384,6 +534,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="seconds of CPU work for the oracle baseline (0 disables)")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other workloads (64x64 latency, 16x256x256, 2x4096x4096 C=16)")
     ap.add_argument("--serving-requests", type=int, default=4096)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -466,32 +618,42 @@ def main():
     P = pair_count(wl.pos, wl.sigma, wl.H, wl.W, wl.radius)
     log(f"pairs inside the radius P = {P} ({time.perf_counter() - t0:.1f} s to count)")
     C = wl.C
-    ops_fwd_pair = fwd_ops(C)
-    ops_bwd_pair = bwd_ops(C)
+    ops = {"forward": (fwd_ops(C), fwd_ops_impl(C)), "bwd_point": (bwd_ops(C), bwd_ops_impl(C))}
     dom = max(kernels.items(), key=lambda kv: kv[1]["avg_us"])
     name, info = dom
-    if name == "forward":
-        work_units = P * ops_fwd_pair
-    elif name == "bwd_point":
-        work_units = P * ops_bwd_pair
-    else:
-        work_units = None
     roof = None
-    if work_units is not None:
-        achieved = work_units / (info["avg_us"] * 1e-6) / 1e12
+    if name in ops:
+        m, im = ops[name]
+        achieved = P * m / (info["avg_us"] * 1e-6) / 1e12
         roof = {"bound": "alu", "kernel": name, "achieved": round(achieved, 3),
                 "peak": round(VALU_PEAK_TLANEOPS, 2), "unit": "Tlaneop/s",
                 "frac": round(achieved / VALU_PEAK_TLANEOPS, 4),
                 "traffic": forward_traffic() if name == "forward" else None,
-                "work_per_launch": f"P={P} pairs x {ops_fwd_pair if name == 'forward' else ops_bwd_pair} "
-                                   "VALU lane-ops",
+                "work_per_launch": f"P={P} pairs x {m} VALU lane-ops (method count)",
+                "frac_impl": round(P * im / (info["avg_us"] * 1e-6) / 1e12 / VALU_PEAK_TLANEOPS, 4),
+                "impl_ops_per_pair": im,
                 "kernel_avg_us": round(info["avg_us"], 2)}
     other = {}
-    for kname, ops in (("forward", ops_fwd_pair), ("bwd_point", ops_bwd_pair)):
+    for kname, (m, im) in ops.items():
         if kname in kernels:
-            a = P * ops / (kernels[kname]["avg_us"] * 1e-6) / 1e12
+            a = P * m / (kernels[kname]["avg_us"] * 1e-6) / 1e12
             other[kname] = {"avg_us": round(kernels[kname]["avg_us"], 2),
-                            "alu_frac": round(a / VALU_PEAK_TLANEOPS, 4)}
+                            "alu_frac": round(a / VALU_PEAK_TLANEOPS, 4),
+                            "alu_frac_impl": round(a * im / m / VALU_PEAK_TLANEOPS, 4)}
+    binning = sum(kernels[k]["avg_us"] * kernels[k]["launches"] / args.steps
+                  for k in ("bin_keys", "radix_hist", "radix_scan", "radix_scatter", "bin_finish",
+                            "fwd_plan") if k in kernels)
+    del out, saved, work, gp, gs, gv, G, graph, graph_fwd, ref
+    torch.cuda.empty_cache()
+
+    configs = None
+    if not args.no_configs:
+        configs = {
+            "cfg1_64x64_n4096_c3": latency_small(synth.config1(), 200, 20, log),
+            "cfg2_16x256x256_n65536_c3_fwd": measure_workload(synth.config2(), args.steps,
+                                                              args.warmup, False, log),
+            "cfg5_2x4096x4096_n4M_c16_fwd_bwd": measure_workload(synth.config5(), 5, 2, True, log),
+        }
 
     cpu = None
     if args.cpu_budget > 0:
@@ -528,10 +690,12 @@ def main():
         "fwd_graph_ms": round(ms_fwd_graph, 4),
         "kernels_us": {k: round(v["avg_us"], 2) for k, v in kernels.items()},
         "kernel_alu": other,
+        "binning_us": round(binning, 2),
         "roofline": roof,
         "measured_ceilings": peaks,
         "cpu_baseline": cpu,
         "serving": serving,
+        "configs": configs,
     }
     print(json.dumps(res), flush=True)
 

@@ -175,7 +175,12 @@ typedef struct interp_server_config {
 
 /* One request: a problem with B = 1 and device pointers that must stay valid
  * until the request is DONE or FAILED.  grad_out == NULL: forward only;
- * otherwise the backward runs too and writes the non-NULL grad_* outputs. */
+ * otherwise the backward runs too and writes the non-NULL grad_* outputs.
+ * ready: a hipEvent_t recorded by the caller after the work that produces
+ * the inputs (and last used the output buffers), or NULL.  The batch that
+ * runs the request waits for it on the device before it reads or writes any
+ * of the request's buffers; the event must stay valid until the request is
+ * DONE or FAILED.  With NULL the inputs must already be complete. */
 typedef struct interp_request {
   interp_problem prob;
   const float* pos;
@@ -186,6 +191,7 @@ typedef struct interp_request {
   float* grad_pos;
   float* grad_sigma;
   float* grad_values;
+  void* ready;
 } interp_request;
 
 enum { INTERP_QUEUED = 0, INTERP_RUNNING = 1, INTERP_DONE = 2, INTERP_FAILED = 3 };
@@ -204,9 +210,9 @@ int interp_server_create(const interp_server_config* cfg, interp_server** out);
 
 /* Non-blocking submit.  ENOMEM if the request can never fit the budget,
  * EAGAIN if max_queue requests are pending, EINVAL for a bad request (B must
- * be 1 and C at most 4 on the serving path).  The inputs must already be
- * complete on the device: the server's streams do not wait for other
- * streams.  On success *ticket identifies the request. */
+ * be 1 and C at most 4 on the serving path).  The server's streams are
+ * ordered after the caller's work only through req->ready (see above).  On
+ * success *ticket identifies the request. */
 int interp_submit(interp_server* s, const interp_request* req, uint64_t* ticket);
 
 /* Non-blocking status query.  ENOTFOUND for an unknown ticket.  A ticket is

@@ -42,7 +42,8 @@ class ServerConfig(ctypes.Structure):
 class Request(ctypes.Structure):
     _fields_ = [("prob", InterpProblem), ("pos", c_void_p), ("sigma", c_void_p),
                 ("values", c_void_p), ("out", c_void_p), ("grad_out", c_void_p),
-                ("grad_pos", c_void_p), ("grad_sigma", c_void_p), ("grad_values", c_void_p)]
+                ("grad_pos", c_void_p), ("grad_sigma", c_void_p), ("grad_values", c_void_p),
+                ("ready", c_void_p)]
 
 
 class Status(ctypes.Structure):

@@ -75,21 +75,55 @@ __global__ __launch_bounds__(256) void k_copy(const float4* __restrict__ src, fl
     dst[i] = src[i];
 }
 
+// Streaming copy: each workgroup moves one contiguous span of kSpan float4s
+// per trip, four loads of a thread in flight before its four stores, with
+// non-temporal hints (the data is touched once).  n must be a multiple of
+// 4 * 256 float4s.
+constexpr int kSpan = 4 * 256;
+typedef float f4v __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_copy_stream(const f4v* __restrict__ src,
+                                                     f4v* __restrict__ dst, long long n) {
+  for (long long base = (long long)blockIdx.x * kSpan; base < n; base += (long long)gridDim.x * kSpan) {
+    f4v r[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r[k] = __builtin_nontemporal_load(src + base + k * 256 + threadIdx.x);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) __builtin_nontemporal_store(r[k], dst + base + k * 256 + threadIdx.x);
+  }
+}
+
+// Read-only stream (a sum per thread; one store per workgroup keeps it alive).
+__global__ __launch_bounds__(256) void k_read_stream(const f4v* __restrict__ src, float* out,
+                                                     long long n) {
+  f4v acc = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (long long base = (long long)blockIdx.x * kSpan; base < n; base += (long long)gridDim.x * kSpan) {
+    f4v r[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r[k] = __builtin_nontemporal_load(src + base + k * 256 + threadIdx.x);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc += r[k];
+  }
+  const float s = acc.x + acc.y + acc.z + acc.w;
+  if (s == 1.2345f) out[blockIdx.x & 1023] = s;
+}
+
 }  // namespace
 
 extern "C" {
 
-// which: 0 fma, 1 exp, 2 mix, 3 copy.  blocks: workgroups of 256 threads
-// (0 picks 8 per compute unit for 0-2).  For the copy, n_float4 elements are
-// copied from src to dst.  Returns the number of lane operations (0-2) or
-// bytes moved (3) one launch performs, or -1 on a launch error.
+// which: 0 fma, 1 exp, 2 mix, 3 copy (grid-stride), 4 streaming copy,
+// 5 streaming read.  blocks: workgroups of 256 threads (0 picks 8 per compute
+// unit).  For the copies, n_float4 elements are copied from src to dst (4, 5:
+// n_float4 a multiple of 1024).  Returns the number of lane operations (0-2)
+// or bytes moved (3-5) one launch performs, or -1 on a launch error.
 double gmm_peak_launch(int which, int blocks, void* out, const void* src, void* dst,
                        long long n_float4, void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (blocks <= 0) {
     int dev = 0, cus = 0;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return -1.0;
     blocks = cus * 8;
   }
   const double lanes = (double)blocks * 256.0;
@@ -108,6 +142,16 @@ double gmm_peak_launch(int which, int blocks, void* out, const void* src, void* 
       hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, st, (const float4*)src, (float4*)dst,
                          n_float4);
       return hipGetLastError() == hipSuccess ? 32.0 * (double)n_float4 : -1.0;
+    case 4:
+      if (n_float4 % kSpan) return -1.0;
+      hipLaunchKernelGGL(k_copy_stream, dim3(blocks), dim3(256), 0, st, (const f4v*)src,
+                         (f4v*)dst, n_float4);
+      return hipGetLastError() == hipSuccess ? 32.0 * (double)n_float4 : -1.0;
+    case 5:
+      if (n_float4 % kSpan) return -1.0;
+      hipLaunchKernelGGL(k_read_stream, dim3(blocks), dim3(256), 0, st, (const f4v*)src,
+                         (float*)out, n_float4);
+      return hipGetLastError() == hipSuccess ? 16.0 * (double)n_float4 : -1.0;
     default:
       return -1.0;
   }

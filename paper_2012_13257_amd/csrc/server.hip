@@ -304,8 +304,15 @@ class GpuExecutor {
       u[PH_BSIG] = bwd && !g.per_point && r.grad_sigma ? 1 : 0;
       for (int ph = 0; ph < PH_COUNT; ++ph) T->units[ph][i + 1] = T->units[ph][i] + u[ph];
     }
+    // the batch starts after every event its requests were submitted with
+    hipError_t e;
+    for (int i = 0; i < nj; ++i) {
+      if (!jobs[i]->req.r.ready) continue;
+      e = hipStreamWaitEvent(x.stream, static_cast<hipEvent_t>(jobs[i]->req.r.ready), 0);
+      if (e != hipSuccess) return fail_hip(e, "hipStreamWaitEvent(ready)");
+    }
     const size_t bytes = offsetof(JobTable, view) + sizeof(ImageView) * (size_t)nj;
-    hipError_t e = hipMemcpyAsync(x.dtab, T, bytes, hipMemcpyHostToDevice, x.stream);
+    e = hipMemcpyAsync(x.dtab, T, bytes, hipMemcpyHostToDevice, x.stream);
     if (e != hipSuccess) return fail_hip(e, "hipMemcpyAsync(table)");
     e = hipGraphLaunch(x.exec[need_passes - 1][need_bwd ? 1 : 0], x.stream);
     if (e != hipSuccess) return fail_hip(e, "hipGraphLaunch");

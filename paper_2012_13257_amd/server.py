@@ -6,11 +6,13 @@
     ...
     res = srv.result(t)   # None while queued/running; dict when done
 
-Every request is one image (B = 1) with C <= 4 channels.  Inputs must be
-complete on the device before submit (the server's streams do not wait for
-other streams); outputs are allocated here and returned once the request is
-done.  The binding keeps every tensor of a request alive until its result
-has been collected.
+Every request is one image (B = 1) with C <= 4 channels.  submit records an
+event on torch's current stream after the request's outputs are allocated,
+and the batch that runs the request waits for it on the device, so inputs
+produced by earlier work on that stream (and output memory the caching
+allocator hands back) are safe to use without a host synchronisation.  The
+binding keeps every tensor of a request, and the event, alive until its
+result has been collected.
 """
 from __future__ import annotations
 
@@ -65,6 +67,10 @@ class Server:
             if "values" in grads:
                 keep["grad_values"] = gb["values"] if "values" in gb else torch.empty_like(values)
                 req.grad_values = keep["grad_values"].data_ptr()
+        ready = torch.cuda.Event()
+        ready.record(torch.cuda.current_stream(self._device))
+        keep["ready"] = ready
+        req.ready = ready.cuda_event
         ticket = ctypes.c_uint64()
         _lib.check("interp_submit", _lib.lib().interp_submit(self._h, ctypes.byref(req),
                                                              ctypes.byref(ticket)))

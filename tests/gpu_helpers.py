@@ -33,6 +33,15 @@ def saved_Z(saved):
     return saved.buf[off: off + 4 * n].view(torch.float32).reshape(p.B, p.H, p.W)
 
 
+def saved_reach(saved):
+    """The per-image reach [B] (largest f32(radius * sigma)) stored after Z."""
+    import torch
+    p = saved.prob
+    off = saved.addr - saved.buf.data_ptr()
+    zbytes = (4 * p.B * p.H * p.W + 255) // 256 * 256
+    return saved.buf[off + zbytes: off + zbytes + 4 * p.B].view(torch.float32)
+
+
 def run_forward(wl, tile=8):
     from paper_2012_13257_amd import interp
     import torch
@@ -63,6 +72,21 @@ def check_forward_pixels(out_g, Z_g, ref, where=""):
                            f"{float((err / np.maximum(scale, 1e-300)).max()):.3g}")
     rel = err[nz] / np.maximum(scale[nz], 1e-300)
     return float(rel.max()) if rel.size else 0.0
+
+
+def check_out_only(out_g, ref, where=""):
+    """out_g [n, C] (GPU) vs the oracle where the GPU's Z is not available:
+    pixels the oracle leaves empty must be exactly 0, the others within the
+    scale-aware tolerance."""
+    o_ref = ref["out"]
+    out_g = np.asarray(out_g, np.float64)
+    empty = ref["Z"] == 0
+    assert np.all(out_g[empty] == 0), f"{where}: empty pixel with non-zero output"
+    scale = np.maximum(np.abs(o_ref), ref["S"])
+    err = np.abs(out_g - o_ref)
+    bad = err > FWD_RTOL * scale
+    assert not bad.any(), (f"{where}: {int(bad.sum())} outputs beyond tolerance; worst rel "
+                           f"{float((err / np.maximum(scale, 1e-300)).max()):.3g}")
 
 
 def check_grad(g_gpu, g_ref, scale, where=""):

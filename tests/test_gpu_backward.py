@@ -46,36 +46,80 @@ def test_backward_shared_sigma_batch():
     _full_backward_check(synth.random_workload(751, 3, 400, 24, 30, C=3, sigma=0.9))
 
 
+def _densest_bin_points(wl, b, k, tile=8):
+    """k points of image b taken from its most populated tile x tile bins."""
+    key = (np.floor(wl.pos[b, :, 1] / tile).astype(np.int64) * (wl.W // tile + 1)
+           + np.floor(wl.pos[b, :, 0] / tile).astype(np.int64))
+    vals, counts = np.unique(key, return_counts=True)
+    dense = vals[np.argsort(counts)[::-1][:4]]
+    members = np.nonzero(np.isin(key, dense))[0]
+    return np.random.default_rng(k).choice(members, k, replace=False)
+
+
 def test_backward_cfg3_sampled_points():
+    """256 points of the 1024x1024 workload: random ones, the 16 with the
+    largest sigma and 32 from the four densest bins."""
     wl = synth.config3()
     say("backward cfg3 sampled")
     G = wl.grad_out()
     gp, gs, gv = _gpu_grads(wl, G)
     rng = np.random.default_rng(77)
-    pts = rng.choice(wl.N, 48, replace=False)
+    special = np.concatenate([np.argsort(wl.sigma[0])[-16:], _densest_bin_points(wl, 0, 32)])
+    rest = rng.choice(np.setdiff1d(np.arange(wl.N), special), 256 - np.unique(special).size,
+                      replace=False)
+    pts = np.unique(np.concatenate([special, rest]))
+    assert pts.size == 256
     ref = oracle.backward_points(wl.pos, wl.sigma, wl.values, G, wl.H, wl.W, wl.radius, 0, pts,
-                                 workers=oracle.default_workers(), block=3)
+                                 workers=oracle.default_workers(), block=4)
     check_grad(gp[0, pts], ref["grad_pos"], ref["scale_pos"], "cfg3 pos")
     check_grad(gv[0, pts], ref["grad_values"], ref["scale_values"], "cfg3 values")
     check_grad(gs[0, pts], ref["grad_sigma"], ref["scale_sigma"], "cfg3 sigma")
 
 
 def test_backward_cfg5_sampled_points():
-    # 2 x 4096x4096, C=16, sigma up to 3: points of the second image (the batch
-    # offset), at random and the four with the largest disks, against the
-    # oracle's per-point brute force
+    """2 x 4096x4096, C=16, sigma up to 3: 32 points of the second image (the
+    batch offset) -- random ones, the four with the largest disks and four
+    from the densest bins -- against the oracle's per-point brute force."""
     wl = synth.config5()
     say("backward cfg5 sampled")
     G = wl.grad_out()
     gp, gs, gv = _gpu_grads(wl, G)
     rng = np.random.default_rng(78)
-    pts = np.unique(np.concatenate([rng.choice(wl.N, 12, replace=False),
-                                    np.argsort(wl.sigma[1])[-4:]]))
+    special = np.concatenate([np.argsort(wl.sigma[1])[-4:], _densest_bin_points(wl, 1, 4)])
+    rest = rng.choice(np.setdiff1d(np.arange(wl.N), special), 32 - np.unique(special).size,
+                      replace=False)
+    pts = np.unique(np.concatenate([special, rest]))
+    assert pts.size == 32
     ref = oracle.backward_points(wl.pos, wl.sigma, wl.values, G, wl.H, wl.W, wl.radius, 1, pts,
                                  workers=oracle.default_workers(), block=1)
     check_grad(gp[1, pts], ref["grad_pos"], ref["scale_pos"], "cfg5 pos")
     check_grad(gv[1, pts], ref["grad_values"], ref["scale_values"], "cfg5 values")
     check_grad(gs[1, pts], ref["grad_sigma"], ref["scale_sigma"], "cfg5 sigma")
+
+
+@pytest.mark.parametrize("C,sigma", [(3, (0.5, 2.5)), (3, 1.3), (8, (0.5, 2.5))])
+def test_backward_points_outside_image_and_dense_bin(C, sigma):
+    """Points just outside the border whose disks reach in, far-away points,
+    a 5000-point bin: every gradient of the image against the oracle."""
+    from test_gpu_forward import _outside_workload
+    wl = _outside_workload(95 + C, C, sigma, values="normal" if C > 4 else "uniform")
+    _full_backward_check(wl)
+
+
+def test_backward_empty_and_single_point():
+    say("backward N=0")
+    for sig in (np.zeros((2, 0), np.float32), np.array([0.8, 1.1], np.float32)):
+        wl0 = synth.Workload("empty", np.zeros((2, 0, 2), np.float32), sig,
+                             np.zeros((2, 0, 3), np.float32), 17, 9, 3.0, grad_seed=3)
+        gp, gs, gv = _gpu_grads(wl0, wl0.grad_out())
+        assert gp.shape == (2, 0, 2) and gv.shape == (2, 0, 3)
+        assert gs.shape == sig.shape and np.all(gs == 0)
+    say("backward N=1")
+    rng = np.random.default_rng(2)
+    for sig in (np.array([[1.2]], np.float32), np.array([1.2], np.float32)):
+        wl1 = synth.Workload("one", np.array([[[4.3, 5.6]]], np.float32), sig,
+                             rng.random((1, 1, 3), dtype=np.float32), 12, 11, 3.0, grad_seed=4)
+        _full_backward_check(wl1)
 
 
 def test_backward_partition_of_unity_cfg3():

@@ -4,7 +4,7 @@ import pytest
 
 import oracle
 from paper_2012_13257_amd import synth
-from gpu_helpers import check_forward_pixels, run_forward, saved_Z, say
+from gpu_helpers import check_forward_pixels, run_forward, saved_reach, saved_Z, say
 
 pytestmark = pytest.mark.gpu
 
@@ -101,9 +101,25 @@ def test_forward_empty_and_single_point():
     _full_forward_check(wl1)
 
 
-def test_forward_cfg2_one_image_full_and_batch_sampled():
+def test_forward_cfg2_one_image_full():
+    """Image 0 of the 16 x 256x256 jittered-grid batch, every pixel against
+    the oracle's brute force over all 65536 points of that image."""
     wl = synth.config2()
-    say("forward cfg2", wl.B, wl.N)
+    say("forward cfg2 image 0 full", wl.B, wl.N)
+    out, saved, _, _ = run_forward(wl)
+    out = out.cpu().numpy()[0]
+    Zg = saved_Z(saved).cpu().numpy()[0]
+    ref = oracle.forward(wl.pos[:1], wl.sigma[:1], wl.values[:1], wl.H, wl.W, wl.radius,
+                         workers=oracle.default_workers())
+    r = {"out": ref["out"][0].transpose(1, 2, 0).reshape(-1, wl.C), "Z": ref["Z"][0].ravel(),
+         "S": ref["S"][0].transpose(1, 2, 0).reshape(-1, wl.C)}
+    check_forward_pixels(out.transpose(1, 2, 0).reshape(-1, wl.C), Zg.ravel(), r, "cfg2 image 0")
+
+
+def test_forward_cfg2_batch_sampled():
+    """2048 pixels drawn over all 16 images of the batch (the batch offsets)."""
+    wl = synth.config2()
+    say("forward cfg2 batch sampled", wl.B, wl.N)
     out, saved, _, _ = run_forward(wl)
     out = out.cpu().numpy()
     Zg = saved_Z(saved).cpu().numpy()
@@ -117,15 +133,20 @@ def test_forward_cfg2_one_image_full_and_batch_sampled():
     check_forward_pixels(out[b, :, v, u], Zg[b, v, u], ref, "cfg2 sampled")
 
 
-def _densest_block(wl, b):
-    cnt, _, _ = np.histogram2d(wl.pos[b, :, 1], wl.pos[b, :, 0], bins=[wl.H // 8, wl.W // 8],
-                               range=[[0, wl.H // 8 * 8], [0, wl.W // 8 * 8]])
-    by, bx = np.unravel_index(np.argmax(cnt), cnt.shape)
-    return by * 8, bx * 8
+def _densest_tiles(wl, b, side, k):
+    """Top-left corners (row, col) of the k most populated side x side tiles of image b."""
+    cnt, _, _ = np.histogram2d(wl.pos[b, :, 1], wl.pos[b, :, 0],
+                               bins=[wl.H // side, wl.W // side],
+                               range=[[0, wl.H // side * side], [0, wl.W // side * side]])
+    flat = np.argsort(cnt.ravel())[::-1][:k]
+    return [(int(i // cnt.shape[1]) * side, int(i % cnt.shape[1]) * side) for i in flat]
 
 
-def _sampled_check(wl, n_random, seed, tile=8):
-    say("forward sampled", wl.name, "tile", tile)
+def _sampled_check(wl, n_random, seed, tile=8, dense_tiles=1, dense_side=8):
+    """n_random random pixels over the batch, every pixel of the dense_tiles
+    most populated dense_side x dense_side tiles of each image, and part of
+    the last row (the ragged tail of the block grid at odd sizes)."""
+    say("forward sampled", wl.name, "tile", tile, "pixels", n_random)
     out, saved, _, _ = run_forward(wl, tile)
     out = out.cpu().numpy()
     Zg = saved_Z(saved).cpu().numpy()
@@ -135,12 +156,12 @@ def _sampled_check(wl, n_random, seed, tile=8):
     vs.append(rng.integers(0, wl.H, n_random))
     us.append(rng.integers(0, wl.W, n_random))
     for b in range(wl.B):
-        v0, u0 = _densest_block(wl, b)
-        vv, uu = np.meshgrid(np.arange(v0, v0 + 8), np.arange(u0, u0 + 8), indexing="ij")
-        bs.append(np.full(64, b))
-        vs.append(vv.ravel())
-        us.append(uu.ravel())
-    # the last row and column (ragged tail of the block grid at odd sizes)
+        for v0, u0 in _densest_tiles(wl, b, dense_side, dense_tiles):
+            vv, uu = np.meshgrid(np.arange(v0, v0 + dense_side), np.arange(u0, u0 + dense_side),
+                                 indexing="ij")
+            bs.append(np.full(vv.size, b))
+            vs.append(vv.ravel())
+            us.append(uu.ravel())
     bs.append(np.zeros(16, np.int64))
     vs.append(np.full(16, wl.H - 1))
     us.append(rng.integers(0, wl.W, 16))
@@ -153,11 +174,55 @@ def _sampled_check(wl, n_random, seed, tile=8):
 
 
 def test_forward_cfg3_sampled():
-    _sampled_check(synth.config3(), 1024, 33)
+    """4096 random pixels plus every pixel of the 4 densest 16x16 tiles."""
+    _sampled_check(synth.config3(), 4096, 33, dense_tiles=4, dense_side=16)
 
 
 def test_forward_cfg5_sampled():
-    _sampled_check(synth.config5(), 192, 55)
+    """4096 random pixels over both images plus the densest 16x16 tile of each."""
+    _sampled_check(synth.config5(), 4096, 55, dense_tiles=1, dense_side=16)
+
+
+def test_reach_is_bit_exact():
+    """The stored per-image reach is the largest f32(radius * sigma) (a max is
+    order-free, so it is exact), for per-point and shared sigma."""
+    for wl in (synth.random_workload(91, 3, 2000, 40, 50, C=2, sigma=(0.5, 3.0)),
+               synth.random_workload(92, 2, 300, 30, 20, C=1, sigma=1.7),
+               synth.config3()):
+        say("reach", wl.name, wl.B, wl.N)
+        _, saved, _, _ = run_forward(wl)
+        got = saved_reach(saved).cpu().numpy()
+        assert np.array_equal(got, oracle.reach(wl.sigma, wl.radius, wl.N))
+
+
+def _outside_workload(seed, C, sigma, values="uniform"):
+    """Points inside, on the border, just outside (whose disks reach in) and
+    far away, plus one 8x8 bin holding 5000 points, on a 40 x 50 image."""
+    rng = np.random.default_rng(seed)
+    H, W = 40, 50
+    pts = [[-1.5, 10.2], [W + 0.7, 20.4], [25.3, H + 1.0], [12.0, -2.25], [-0.5, -0.5],
+           [W - 0.01, H - 0.01], [W + 2.0, H + 2.0], [8.0, 8.0], [16.0, 0.0],
+           [-1e6, -1e6], [1e6, 2.0], [0.0, 1e6], [-7.5, 30.0]]
+    big = np.column_stack([rng.uniform(16.0, 23.99, 5000), rng.uniform(8.0, 15.99, 5000)])
+    allp = np.concatenate([np.array(pts), big, rng.random((600, 2)) * [W, H]]).astype(np.float32)
+    allp = allp[rng.permutation(allp.shape[0])]
+    N = allp.shape[0]
+    if isinstance(sigma, float):
+        sig = np.full((1,), sigma, np.float32)
+    else:
+        sig = rng.uniform(sigma[0], sigma[1], (1, N)).astype(np.float32)
+    if values == "normal":
+        val = rng.standard_normal((1, N, C)).astype(np.float32)
+    else:
+        val = rng.random((1, N, C), dtype=np.float32)
+    return synth.Workload(f"outside_c{C}", allp[None], sig, val, H, W, 3.0, grad_seed=seed + 1)
+
+
+@pytest.mark.parametrize("C,sigma", [(3, (0.5, 2.5)), (3, 1.3), (8, (0.5, 2.5))])
+def test_forward_points_outside_image_and_dense_bin(C, sigma):
+    wl = _outside_workload(95 + C, C, sigma, values="normal" if C > 4 else "uniform")
+    _check_bins(wl)
+    _full_forward_check(wl)
 
 
 def test_three_radix_passes_bins_and_sampled_forward():

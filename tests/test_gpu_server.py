@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 from paper_2012_13257_amd import synth
-from gpu_helpers import check_forward_pixels, say
+from gpu_helpers import check_grad, check_out_only, say
 
 pytestmark = pytest.mark.gpu
 
@@ -75,24 +75,69 @@ def test_server_results_equal_single_call_alone_and_in_mix():
 
 
 def test_server_matches_oracle_on_small_requests():
-    import torch
+    """Forward of every request and, for the requests that ask for it, every
+    gradient, against the oracle (the server exports no Z: empty pixels are
+    checked through the output, which must be exactly 0 there)."""
     from paper_2012_13257_amd.server import Server
-    reqs = _requests(6, 99, sides=(24, 40))
+    reqs = _requests(8, 99, sides=(24, 40))
+    reqs[0][0].backward = reqs[3][0].backward = True
+    reqs[1][0].backward = False
     with Server(budget_bytes=256 << 20, max_slots=8) as srv:
         dev = [_dev(wl) for _, wl in reqs]
-        torch.cuda.synchronize()
-        ts = [srv.submit(p, s, v, wl.H, wl.W, wl.radius) for (_, wl), (p, s, v, _) in zip(reqs, dev)]
+        say("server vs oracle")
+        ts = [srv.submit(p, s, v, wl.H, wl.W, wl.radius, grad_out=G if r.backward else None)
+              for (r, wl), (p, s, v, G) in zip(reqs, dev)]
         assert srv.drain(60000)
+        nb = 0
         for (r, wl), t in zip(reqs, ts):
             res = srv.result(t)
-            ref = oracle.forward(wl.pos, wl.sigma, wl.values, wl.H, wl.W, wl.radius)
+            assert res["state"] == 2, res
+            if r.backward:
+                G = wl.grad_out()
+                ref = oracle.backward(wl.pos, wl.sigma, wl.values, G, wl.H, wl.W, wl.radius,
+                                      workers=oracle.default_workers())
+                fwd = ref["fwd"]
+                check_grad(res["grad_pos"].cpu().numpy(), ref["grad_pos"], ref["scale_pos"],
+                           f"server request {r.index} pos")
+                check_grad(res["grad_values"].cpu().numpy(), ref["grad_values"],
+                           ref["scale_values"], f"server request {r.index} values")
+                check_grad(res["grad_sigma"].cpu().numpy(), ref["grad_sigma"], ref["scale_sigma"],
+                           f"server request {r.index} sigma")
+                nb += 1
+            else:
+                fwd = oracle.forward(wl.pos, wl.sigma, wl.values, wl.H, wl.W, wl.radius)
             og = res["out"].cpu().numpy().transpose(0, 2, 3, 1).reshape(-1, wl.C)
-            r_ = {"out": ref["out"].transpose(0, 2, 3, 1).reshape(-1, wl.C), "Z": ref["Z"].ravel(),
-                  "S": ref["S"].transpose(0, 2, 3, 1).reshape(-1, wl.C)}
-            # Z of the request is not exported by the server: use the oracle's own
-            # empty-pixel pattern through the output values
-            check_forward_pixels(og, np.where(ref["Z"].ravel() > 0, ref["Z"].ravel(), 0.0), r_,
-                                 f"server request {r.index}")
+            r_ = {"out": fwd["out"].transpose(0, 2, 3, 1).reshape(-1, wl.C), "Z": fwd["Z"].ravel(),
+                  "S": fwd["S"].transpose(0, 2, 3, 1).reshape(-1, wl.C)}
+            check_out_only(og, r_, f"server request {r.index}")
+        assert nb >= 2
+
+
+def test_server_waits_for_the_callers_stream():
+    """Inputs written by a kernel still running on torch's stream at submit
+    time: the server's batch waits for the event submit records, so the
+    result equals the single-call one on the final inputs."""
+    import torch
+    from paper_2012_13257_amd.server import Server
+    (r, wl), = _requests(1, 123, sides=(128,))
+    p, s, v, _ = _dev(wl)
+    torch.cuda.synchronize()
+    ref = _single(p, s, v, None, wl, False)
+    torch.cuda.synchronize()
+    with Server(budget_bytes=256 << 20, max_slots=4) as srv:
+        say("server ordered after the caller's stream")
+        v2 = torch.zeros_like(v)
+        # a long chain of work on the current stream ends by writing the values
+        junk = torch.randn(4096, 4096, device="cuda")
+        for _ in range(8):
+            junk = junk @ junk
+            junk = junk / junk.norm()
+        v2.copy_(v + 0.0 * junk[0, 0])
+        t = srv.submit(p, s, v2, wl.H, wl.W, wl.radius)
+        assert srv.drain(60000)
+        res = srv.result(t)
+        assert res["state"] == 2
+        assert torch.equal(res["out"], ref["out"])
 
 
 def test_server_budget_and_argument_errors():
