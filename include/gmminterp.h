@@ -101,6 +101,29 @@ int interp_forward(const interp_problem* prob, const float* pos, const float* si
                    const float* values, float* out, void* saved, size_t saved_size,
                    void* workspace, size_t workspace_size, void* stream);
 
+/* Forward pass without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc).  Same arguments, results and errors as
+ * interp_forward, but the workspace is the library's own static scratch: a
+ * device array of INTERP_NOALLOC_SCRATCH_BYTES (64 MiB) per GPU, reserved
+ * when the library's code is loaded onto that GPU and held until the process
+ * ends.  No hipMalloc/hipFree and no other allocating call is made (the
+ * interp_profile_* hooks do not record this call's kernels).
+ *   out, saved   as for interp_forward (caller-allocated outputs; saved may
+ *                then go to interp_backward with a caller workspace)
+ * EINVAL if the problem's forward workspace exceeds the scratch (the message
+ * gives both sizes); nothing is launched then.  The first call on a device
+ * looks up that device's copy of the scratch (the stream must belong to the
+ * current device).  Every call on one GPU shares that GPU's scratch: calls
+ * that overlap in time on one GPU (different streams or threads) race and
+ * give undefined results; calls ordered on one stream are safe.  The
+ * scratch keeps the last call's contents; everything the forward needs
+ * zeroed is cleared by its own kernels. */
+#define INTERP_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int interp_forward_noalloc(const interp_problem* prob, const float* pos, const float* sigma,
+                           const float* values, float* out, void* saved, size_t saved_size,
+                           void* stream);
+
 /* Backward pass: gradients of a scalar loss L given grad_out = dL/d out.
  *   pos, sigma, values, out, saved   exactly as given to / produced by the
  *                                    matching interp_forward call

@@ -21,6 +21,8 @@ INTERP_EAGAIN = -3
 INTERP_EHIP = -4
 INTERP_ENOTFOUND = -5
 
+NOALLOC_SCRATCH_BYTES = 64 << 20   # INTERP_NOALLOC_SCRATCH_BYTES
+
 QUEUED, RUNNING, DONE, FAILED = 0, 1, 2, 3
 
 c_int32 = ctypes.c_int32
@@ -53,7 +55,8 @@ class Status(ctypes.Structure):
 
 # every symbol include/gmminterp.h declares
 EXPORTS = [
-    "interp_workspace_bytes", "interp_saved_bytes", "interp_forward", "interp_backward",
+    "interp_workspace_bytes", "interp_saved_bytes", "interp_forward", "interp_forward_noalloc",
+    "interp_backward",
     "interp_debug_bins", "interp_last_error", "interp_profile_enable", "interp_profile_read",
     "interp_server_create", "interp_submit",
     "interp_poll", "interp_server_drain", "interp_server_destroy",
@@ -72,6 +75,9 @@ def _declare(L):
     L.interp_forward.argtypes = [P, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
                                  c_void_p, c_size_t, c_void_p]
     L.interp_forward.restype = ctypes.c_int
+    L.interp_forward_noalloc.argtypes = [P, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                         c_size_t, c_void_p]
+    L.interp_forward_noalloc.restype = ctypes.c_int
     L.interp_backward.argtypes = [P, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
                                   c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
     L.interp_backward.restype = ctypes.c_int

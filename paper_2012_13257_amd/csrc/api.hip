@@ -35,6 +35,8 @@ struct ProfRecord {
 std::mutex g_prof_mu;
 std::vector<ProfRecord> g_prof;
 std::atomic<int> g_prof_on{0};
+// set while a call that must not create events (interp_forward_noalloc) launches
+thread_local bool g_prof_suppress = false;
 
 void prof_clear_locked() {
   for (auto& r : g_prof) {
@@ -46,7 +48,7 @@ void prof_clear_locked() {
 }  // namespace
 
 ProfRange::ProfRange(const char* name, hipStream_t s) : token(-1), st(s) {
-  if (!g_prof_on.load(std::memory_order_relaxed)) return;
+  if (g_prof_suppress || !g_prof_on.load(std::memory_order_relaxed)) return;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
   ProfRecord r{name, nullptr, nullptr};
@@ -67,6 +69,42 @@ ProfRange::~ProfRange() {
     stop = g_prof[token].stop;
   }
   hipEventRecord(stop, st);
+}
+
+// ---------------------------------------------------------------------------
+// Static scratch of interp_forward_noalloc
+// ---------------------------------------------------------------------------
+// The forward's workspace for callers that cannot allocate: a file-scope
+// device array, one copy per GPU the library runs on, held until the process
+// ends.  Host code never passes the array's name to a kernel (on the host it
+// is only a stand-in for the symbol): the device address of each GPU's copy
+// is looked up once per device with hipGetSymbolAddress and used instead.
+constexpr size_t kStaticScratchBytes = INTERP_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};  // device address of `scratch`, per device
+}  // namespace
+
+// The current device's copy of the scratch array (looked up on the first call
+// on that device, with that device current).
+static int static_scratch(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(INTERP_EINVAL, "device ordinal out of range");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return fail_hip(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(INTERP_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return INTERP_OK;
 }
 
 static bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
@@ -129,6 +167,41 @@ int interp_forward(const interp_problem* prob, const float* pos, const float* si
                                  nullptr, nullptr);
   int* fplan = reinterpret_cast<int*>(static_cast<char*>(workspace) + L.fplan);
   hipError_t e = launch_forward_all(g, v0, fplan, st);
+  if (e != hipSuccess) return fail_hip(e, "forward kernels");
+  g_last_error.clear();
+  return INTERP_OK;
+}
+
+int interp_forward_noalloc(const interp_problem* prob, const float* pos, const float* sigma,
+                           const float* values, float* out, void* saved, size_t saved_size,
+                           void* stream) {
+  Geometry g;
+  std::string m = make_geometry(prob, &g);
+  if (!m.empty()) return fail(INTERP_EINVAL, m);
+  const Layout L = make_layout(g);
+  if (L.fwd_work_bytes > kStaticScratchBytes)
+    return fail(INTERP_EINVAL, "problem needs " + std::to_string(L.fwd_work_bytes) +
+                                   " bytes of forward workspace; the static scratch of "
+                                   "interp_forward_noalloc holds " +
+                                   std::to_string(kStaticScratchBytes) +
+                                   " (use interp_forward with a caller workspace)");
+  void* work = nullptr;
+  int rc = static_scratch(&work);
+  if (rc != INTERP_OK) return rc;
+  Geometry g2;
+  Layout L2;
+  rc = check_io(prob, &g2, &L2, pos, sigma, values, saved, saved_size, work, L.work_bytes);
+  if (rc != INTERP_OK) return rc;
+  if (!out || !aligned(out, 4)) return fail(INTERP_EINVAL, "out must be a non-NULL 4-byte aligned pointer");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  ImageView v0 = make_view(g, L, saved, work, pos, sigma, values, out, nullptr, nullptr, nullptr,
+                           nullptr);
+  v0.prec = nullptr;  // backward-only parts of the layout lie beyond the scratch
+  v0.gpart = nullptr;
+  int* fplan = reinterpret_cast<int*>(static_cast<char*>(work) + L.fplan);
+  g_prof_suppress = true;
+  hipError_t e = launch_forward_all(g, v0, fplan, st);
+  g_prof_suppress = false;
   if (e != hipSuccess) return fail_hip(e, "forward kernels");
   g_last_error.clear();
   return INTERP_OK;

@@ -92,7 +92,7 @@ struct Layout {
   size_t Z, reach, offset, perm, geo, col, saved_bytes;
   // workspace
   size_t binof, keysF, kA, vA, kB, vB, geoA, colA, geoB, colB, hist, dtot, rpart, prec, gpart, fplan,
-      work_bytes;
+      fwd_work_bytes, work_bytes;
 };
 
 inline Layout make_layout(const Geometry& g) {
@@ -122,11 +122,13 @@ inline Layout make_layout(const Geometry& g) {
   L.hist = o;   o = align_up(o + B * size_t(256) * g.ntiles * 4);
   L.dtot = o;   o = align_up(o + B * size_t(256) * 4);
   L.rpart = o;  o = align_up(o + B * size_t(g.units256) * 4 + 4);
-  L.prec = o;   o = align_up(o + B * HW * size_t(g.CP) * 4);
-  L.gpart = o;  o = align_up(o + B * size_t(g.units256) * 4 + 4);
   // forward work order: 64 counters (list sizes), then kPlanBuckets lists of
   // up to 2 * B * fwd_units work items
   L.fplan = o;  o = align_up(o + (64 + size_t(kPlanBuckets) * 2 * B * g.fwd_units) * 4);
+  // everything above is all the forward uses; the rest is the backward's
+  L.fwd_work_bytes = o;
+  L.prec = o;   o = align_up(o + B * HW * size_t(g.CP) * 4);
+  L.gpart = o;  o = align_up(o + B * size_t(g.units256) * 4 + 4);
   L.work_bytes = o;
   return L;
 }

@@ -18,8 +18,8 @@ import torch
 
 from . import _lib
 
-__all__ = ["interpolate", "InterpFunction", "forward", "backward", "debug_bins", "problem",
-           "aligned_buffer"]
+__all__ = ["interpolate", "InterpFunction", "forward", "forward_noalloc", "backward", "debug_bins",
+           "problem", "aligned_buffer"]
 
 DEFAULT_TILE = 8
 
@@ -100,6 +100,21 @@ def forward(pos, sigma, values, H, W, radius=3.0, tile=DEFAULT_TILE):
                                    _stream(dev))
     _lib.check("interp_forward", rc)
     return out, saved, work
+
+
+def forward_noalloc(pos, sigma, values, out, saved: Saved, H, W, radius=3.0, tile=DEFAULT_TILE):
+    """Runs interp_forward_noalloc into the caller's out [B,C,H,W] and saved
+    state: the library allocates nothing and uses its static per-GPU scratch
+    as the workspace.  Returns out."""
+    prob = problem(pos, sigma, values, H, W, radius, tile)
+    if (out.dtype != torch.float32 or not out.is_cuda or not out.is_contiguous()
+            or tuple(out.shape) != (prob.B, prob.C, prob.H, prob.W)):
+        raise ValueError("out must be a contiguous float32 [B, C, H, W] tensor on the device")
+    rc = _lib.lib().interp_forward_noalloc(ctypes.byref(prob), _ptr(pos), _ptr(sigma),
+                                           _ptr(values), _ptr(out), saved.addr, saved.nbytes,
+                                           _stream(pos.device))
+    _lib.check("interp_forward_noalloc", rc)
+    return out
 
 
 def backward(pos, sigma, values, out, saved: Saved, grad_out, need_pos=True, need_sigma=True,
