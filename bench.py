@@ -394,6 +394,54 @@ def latency_small(wl, steps: int, warmup: int, log):
     return res
 
 
+def optimisation_step_timing(steps: int, warmup: int, log, size: int = 1024,
+                             n_points: int = 1 << 18):
+    """One step of the point / sigma fitting (render through the autograd
+    binding, L1 loss against a synthetic target, backward, Adam update) on a
+    1024x1024 RGB target with 2^18 points and per-point sigma."""
+    import torch
+    from paper_2012_13257_amd import synth
+    from paper_2012_13257_amd.optimize import PointFit, l1_loss
+    target = torch.from_numpy(synth.natural_image(7, 3, size, size)).cuda()
+    fit = PointFit.from_image(target, n_points, 1.0, seed=7, per_point_sigma=True,
+                              learn_pos=True, learn_sigma=True)
+    opt = torch.optim.Adam([{"params": [fit.pos], "lr": 0.05},
+                            {"params": [fit.log_sigma], "lr": 0.02}])
+
+    def step():
+        opt.zero_grad(set_to_none=True)
+        l1_loss(fit.render(), target).backward()
+        opt.step()
+
+    ms, _, _ = time_steps(step, steps, warmup, profile=False)
+    res = {"H": size, "W": size, "C": 3, "N": n_points, "ms_per_step": round(ms, 4),
+           "mpix_s": round(size * size / (ms * 1e-3) / 1e6, 1),
+           "step": "render + L1 + backward (pos, per-point sigma) + Adam"}
+    log(f"optimisation step: {res}")
+    return res
+
+
+def upsampling_timing(steps: int, warmup: int, log, B: int = 16, low: int = 64, s: int = 4):
+    """Gaussian-mixture upsampling of a batch of 16 RGB 64x64 images by 4 (the
+    reconstruction study's operation): one forward call per step."""
+    import torch
+    from paper_2012_13257_amd import reconstruct, synth
+    img = torch.from_numpy(np.stack([synth.natural_image(100 + i, 3, low * s, low * s)
+                                     for i in range(B)])).cuda()
+    lowres = reconstruct.downsample(img, s)
+    pos, val = reconstruct.gmm_points(lowres, s)
+    sig = torch.full((B,), 0.5 * s, device="cuda")
+    from paper_2012_13257_amd import interp
+    with torch.no_grad():
+        fn = lambda: interp.forward(pos, sig, val, low * s, low * s, 3.0)  # noqa: E731
+        ms, _, _ = time_steps(fn, steps, warmup, profile=False)
+    res = {"B": B, "in": low, "factor": s, "out": low * s, "N": low * low, "C": 3,
+           "sigma": 0.5 * s, "ms_per_call": round(ms, 4),
+           "mpix_s": round(B * (low * s) ** 2 / (ms * 1e-3) / 1e6, 1)}
+    log(f"upsampling: {res}")
+    return res
+
+
 def serving_benchmark(log, n_requests: int = 4096, seed: int = 1004, budget_gb: float = 24.0,
                       slots: int = 256):
     """Serving stream (sides 64..1024, N = side^2 * U(0.25, 1), C in {1,3,4},
@@ -653,6 +701,9 @@ def main():
             "cfg2_16x256x256_n65536_c3_fwd": measure_workload(synth.config2(), args.steps,
                                                               args.warmup, False, log),
             "cfg5_2x4096x4096_n4M_c16_fwd_bwd": measure_workload(synth.config5(), 5, 2, True, log),
+            "optimise_1024x1024_n256k_pos_sigma": optimisation_step_timing(args.steps,
+                                                                          args.warmup, log),
+            "upsample_16x64x64_x4": upsampling_timing(args.steps, args.warmup, log),
         }
 
     cpu = None

@@ -161,8 +161,9 @@ class InterpFunction(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, pos, sigma, values, H, W, radius, tile):
-        out, saved, _ = forward(pos, sigma, values, H, W, radius, tile)
+        out, saved, work = forward(pos, sigma, values, H, W, radius, tile)
         ctx.saved_state = saved
+        ctx.work = work  # the backward reuses the forward's workspace
         ctx.save_for_backward(pos, sigma, values, out)
         return out
 
@@ -173,7 +174,8 @@ class InterpFunction(torch.autograd.Function):
         if not (need[0] or need[1] or need[2]):
             return None, None, None, None, None, None, None
         gp, gs, gv = backward(pos, sigma, values, out, ctx.saved_state, grad_out.float(),
-                              need_pos=need[0], need_sigma=need[1], need_values=need[2])
+                              need_pos=need[0], need_sigma=need[1], need_values=need[2],
+                              work=ctx.work)
         return gp, gs, gv, None, None, None, None
 
 

@@ -33,7 +33,7 @@ import numpy as np
 __all__ = [
     "Workload", "uniform_points", "blob_points", "random_workload",
     "config1", "config2", "config3", "config4_trace", "config5",
-    "ServingRequest", "CONFIGS",
+    "ServingRequest", "CONFIGS", "natural_image", "sample_image_points",
 ]
 
 
@@ -263,6 +263,60 @@ def config4_trace(n_requests: int = 4096, rate_per_s: Optional[float] = None,
             t += float(rng.exponential(1.0 / rate_per_s))
         reqs.append(ServingRequest(i, t, side, n, c, s, bwd, seed * 100003 + i))
     return reqs
+
+
+# --------------------------------------------------------------------------
+# Synthetic images (targets of the point optimisation and of the
+# downsample / upsample study)
+# --------------------------------------------------------------------------
+
+def natural_image(seed: int, C: int, H: int, W: int, n_shapes: int = 12) -> np.ndarray:
+    """A [C, H, W] float32 image in [0, 1] with natural-image statistics: a
+    1/f-amplitude random-phase field (smooth shading and texture at every
+    scale) plus n_shapes flat-coloured rectangles and discs with sharp edges
+    (walls, furniture, objects), lit by a smooth gradient."""
+    rng = np.random.default_rng(seed)
+    fy = np.fft.fftfreq(H)[:, None]
+    fx = np.fft.rfftfreq(W)[None, :]
+    f = np.sqrt(fx * fx + fy * fy)
+    f[0, 0] = 1.0
+    img = np.empty((C, H, W), dtype=np.float64)
+    base = rng.uniform(0.2, 0.8, size=C)
+    for c in range(C):
+        spec = (rng.standard_normal(f.shape) + 1j * rng.standard_normal(f.shape)) / f
+        spec[0, 0] = 0.0
+        field = np.fft.irfft2(spec, s=(H, W))
+        field *= 0.12 / max(field.std(), 1e-12)
+        img[c] = base[c] + field
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    for _ in range(n_shapes):
+        col = rng.uniform(0.0, 1.0, size=C)
+        if rng.random() < 0.5:
+            x0, x1 = np.sort(rng.uniform(0, W, 2))
+            y0, y1 = np.sort(rng.uniform(0, H, 2))
+            m = (xx >= x0) & (xx < x1) & (yy >= y0) & (yy < y1)
+        else:
+            cx, cy = rng.uniform(0, W), rng.uniform(0, H)
+            rad = rng.uniform(0.03, 0.2) * min(H, W)
+            m = (xx - cx) ** 2 + (yy - cy) ** 2 <= rad * rad
+        tex = img[:, m] - base[:, None]
+        img[:, m] = col[:, None] + 0.5 * tex
+    g = rng.uniform(-1, 1, size=2)
+    light = 0.85 + 0.15 * (g[0] * (xx / W - 0.5) + g[1] * (yy / H - 0.5))
+    img *= light[None]
+    return np.clip(img, 0.0, 1.0).astype(np.float32)
+
+
+def sample_image_points(rng: np.random.Generator, img: np.ndarray, n: int):
+    """n points uniform over [0, W-1] x [0, H-1] carrying the image's value at
+    the nearest pixel: (pos [n, 2] float32 (x, y), values [n, C] float32)."""
+    C, H, W = img.shape
+    pos = np.empty((n, 2), dtype=np.float32)
+    pos[:, 0] = (rng.random(n) * (W - 1)).astype(np.float32)
+    pos[:, 1] = (rng.random(n) * (H - 1)).astype(np.float32)
+    iu = np.rint(pos[:, 0]).astype(np.int64)
+    iv = np.rint(pos[:, 1]).astype(np.int64)
+    return pos, np.ascontiguousarray(img[:, iv, iu].T)
 
 
 CONFIGS = {1: config1, 2: config2, 3: config3, 5: config5}
