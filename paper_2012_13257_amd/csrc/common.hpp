@@ -113,12 +113,13 @@ inline Layout make_layout(const Geometry& g) {
   L.vA = o;     o = align_up(o + B * N * 4);
   L.kB = o;     o = align_up(o + B * N * 4);
   L.vB = o;     o = align_up(o + B * N * 4);
-  // point records between radix passes (the second set only with 3+ passes)
-  const size_t NB = g.npass >= 3 ? N : 0;
-  L.geoA = o;   o = align_up(o + B * N * 16);
-  L.colA = o;   o = align_up(o + B * N * size_t(g.CS) * 4);
+  // narrow point records (CS = 4) between radix passes (the second set only
+  // with 3+ passes); wide records are read from the inputs by the last pass
+  const size_t NA = g.CS == 4 && g.npass >= 2 ? N : 0, NB = g.CS == 4 && g.npass >= 3 ? N : 0;
+  L.geoA = o;   o = align_up(o + B * NA * 16);
+  L.colA = o;   o = align_up(o + B * NA * 16);
   L.geoB = o;   o = align_up(o + B * NB * 16);
-  L.colB = o;   o = align_up(o + B * NB * size_t(g.CS) * 4);
+  L.colB = o;   o = align_up(o + B * NB * 16);
   L.hist = o;   o = align_up(o + B * size_t(256) * g.ntiles * 4);
   L.dtot = o;   o = align_up(o + B * size_t(256) * 4);
   L.rpart = o;  o = align_up(o + B * size_t(g.units256) * 4 + 4);
@@ -197,8 +198,8 @@ struct ImageView {
   int* binof;               // [N] bin key of each point (point order)
   int* keysF;               // [N] bin keys in sorted order
   int* kA; int* vA; int* kB; int* vB;   // radix ping-pong buffers: keys, point indices
-  float4* geoA; float* colA;            // and the point records (as geo, col)
-  float4* geoB; float* colB;
+  float4* geoA; float4* colA;           // and narrow point records (as geo, col)
+  float4* geoB; float4* colB;
   int* hist;                // [256 * ntiles] per (digit, tile) counts, then offsets
   int* dtot;                // [256] per-digit totals of the current radix pass
   float* rpart;             // [units256] partial maxima of radius*sigma
@@ -234,13 +235,13 @@ __host__ __device__ inline ImageView image_of(const ImageView& v0, int b) {
   v.vA = shift(v0.vA, bb * N);
   v.kB = shift(v0.kB, bb * N);
   v.vB = shift(v0.vB, bb * N);
+  v.geoA = shift(v0.geoA, bb * N);
+  v.colA = shift(v0.colA, bb * N);
+  v.geoB = shift(v0.geoB, bb * N);
+  v.colB = shift(v0.colB, bb * N);
   v.hist = shift(v0.hist, bb * 256 * size_t(v0.ntiles));
   v.dtot = shift(v0.dtot, bb * 256);
   v.rpart = shift(v0.rpart, bb * v0.units256);
-  v.geoA = shift(v0.geoA, bb * N);
-  v.colA = shift(v0.colA, bb * N * v0.CS);
-  v.geoB = shift(v0.geoB, bb * N);
-  v.colB = shift(v0.colB, bb * N * v0.CS);
   v.prec = shift(v0.prec, bb * HW * v0.CP);
   v.gpart = shift(v0.gpart, bb * v0.units256);
   return v;
@@ -281,13 +282,13 @@ inline ImageView make_view(const Geometry& g, const Layout& L, void* saved, void
   v.vA = w ? reinterpret_cast<int*>(w + L.vA) : nullptr;
   v.kB = w ? reinterpret_cast<int*>(w + L.kB) : nullptr;
   v.vB = w ? reinterpret_cast<int*>(w + L.vB) : nullptr;
+  v.geoA = w ? reinterpret_cast<float4*>(w + L.geoA) : nullptr;
+  v.colA = w ? reinterpret_cast<float4*>(w + L.colA) : nullptr;
+  v.geoB = w ? reinterpret_cast<float4*>(w + L.geoB) : nullptr;
+  v.colB = w ? reinterpret_cast<float4*>(w + L.colB) : nullptr;
   v.hist = w ? reinterpret_cast<int*>(w + L.hist) : nullptr;
   v.dtot = w ? reinterpret_cast<int*>(w + L.dtot) : nullptr;
   v.rpart = w ? reinterpret_cast<float*>(w + L.rpart) : nullptr;
-  v.geoA = w ? reinterpret_cast<float4*>(w + L.geoA) : nullptr;
-  v.colA = w ? reinterpret_cast<float*>(w + L.colA) : nullptr;
-  v.geoB = w ? reinterpret_cast<float4*>(w + L.geoB) : nullptr;
-  v.colB = w ? reinterpret_cast<float*>(w + L.colB) : nullptr;
   v.prec = w ? reinterpret_cast<float*>(w + L.prec) : nullptr;
   v.gpart = w ? reinterpret_cast<float*>(w + L.gpart) : nullptr;
   return v;

@@ -237,19 +237,16 @@ __device__ inline void radix_scan_digit(const ImageView& v, int p, int d, int* t
 // and the tile's keys and source slots in digit order.
 __host__ __device__ constexpr int radix_scatter_lds_ints() { return 6 * 256 + 4 + 2 * kRadixTile; }
 
-// unit = one tile: stable scatter of the tile's points by the pass's digit,
-// moving with each key its point index and record (geo, values) -- built
-// from the inputs in the first pass, so the last pass leaves the records in
-// bin order and no gather is needed.  Each wavefront ranks the
-// kRadixTile / 4 consecutive keys it owns in rounds of 64 (equal digits by ballot --
-// multisplit -- and a per-wavefront running count per digit in LDS); the
-// wavefronts' counts then give every key its place in a digit-ordered list of
-// the tile in LDS (wavefronts in index order, so equal digits keep their
-// input order), which is written out so that every digit's entries form one
-// contiguous run in the output.
-// kWide: the records carry more than four values (CS > 4); those are moved
-// after the first four, all loads of an entry before its stores.  The
-// narrow instantiation (CS = 4) keeps the register budget of the common case.
+// unit = one tile: stable scatter of the tile's (key, point index) pairs by
+// the pass's digit.  Each wavefront ranks the kRadixTile / 4 consecutive keys
+// it owns in rounds of 64 (equal digits by ballot -- multisplit -- and a
+// per-wavefront running count per digit in LDS); the wavefronts' counts then
+// give every key its place in a digit-ordered list of the tile in LDS
+// (wavefronts in index order, so equal digits keep their input order), which
+// is written out so that every digit's entries form one contiguous run in the
+// output.  The last pass writes the sorted keys, the permutation and the
+// sorted point records (x, y, k, R2 and the values padded to CS).
+// kWide: the records carry more than four values (CS > 4).
 template <bool kWide = false>
 __device__ inline void radix_scatter(const ImageView& v, int p, int tile, int* lds) {
   int* wrun = lds;                 // [4][256]
@@ -266,8 +263,6 @@ __device__ inline void radix_scatter(const ImageView& v, int p, int tile, int* l
   // buffer choice by value (selecting between fields through the view would
   // make the compiler copy the view to scratch memory)
   int* const kA = v.kA; int* const kB = v.kB; int* const vA = v.vA; int* const vB = v.vB;
-  float4* const geoA = v.geoA; float4* const geoB = v.geoB;
-  float* const colA = v.colA; float* const colB = v.colB;
   const int* kin = first ? v.binof : (in_a ? kA : kB);
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
   const int t0 = tile * kRadixTile;
@@ -330,66 +325,85 @@ __device__ inline void radix_scatter(const ImageView& v, int p, int tile, int* l
   }
   __syncthreads();
   // 4) write out: consecutive entries of one digit go to consecutive places;
-  // all loads of this thread's entries first, then the stores
+  // all loads of this thread's entries first, then the stores.  Narrow
+  // records (CS = 4) travel with their keys through every pass: the first
+  // pass builds them from the inputs (coalesced reads of the tile's points)
+  // and the last leaves them in bin order.  Wide records (more than four
+  // values) cost more to move in every pass than to read once: the passes
+  // before the last move only (key, point index), and the last pass reads
+  // each entry's record from the inputs at its point index.
   int* const keysF = v.keysF; int* const perm = v.perm;
   float4* const geo = v.geo; float* const col = v.col;
-  int* kout = last ? keysF : (out_a ? kA : kB);
-  int* jout = last ? perm : (out_a ? vA : vB);
-  float4* gout = last ? geo : (out_a ? geoA : geoB);
-  float* cout = last ? col : (out_a ? colA : colB);
+  float4* const geoA = v.geoA; float4* const geoB = v.geoB;
+  float4* const colA = v.colA; float4* const colB = v.colB;
   const int* jin = in_a ? vA : vB;
-  const float4* gin = in_a ? geoA : geoB;
-  const float* cin = in_a ? colA : colB;
-  constexpr int kHalf = kRadixItems;  // entries per batch of loads
-  int epos[kRadixItems];
+  int ek[kRadixItems], ej[kRadixItems], epos[kRadixItems];
+  float4 eg[kRadixItems], ec[kRadixItems];
 #pragma unroll
-  for (int h = 0; h < kRadixItems; h += kHalf) {
-    int ek[kHalf], ej[kHalf];
-    float4 eg[kHalf], ec[kHalf];
-#pragma unroll
-    for (int q = 0; q < kHalf; ++q) {
-      const int e = min(t + (h + q) * 256, tn - 1);
-      ek[q] = skey[e];
-      const int src = t0 + ssrc[e];
-      const int d = (ek[q] >> shift) & mask;
-      epos[h + q] = base[d] + e - tstart[d];
+  for (int q = 0; q < kRadixItems; ++q) {
+    const int e = min(t + q * 256, tn - 1);
+    ek[q] = skey[e];
+    const int src = t0 + ssrc[e];
+    const int d = (ek[q] >> shift) & mask;
+    epos[q] = base[d] + e - tstart[d];
+    ej[q] = first ? src : jin[src];
+    if constexpr (!kWide) {
       if (first) {
-        ej[q] = src;
         eg[q] = point_geo(v, src);
         ec[q] = point_values4(v, src, 0);
       } else {
-        ej[q] = jin[src];
-        eg[q] = gin[src];
-        ec[q] = reinterpret_cast<const float4*>(cin + (size_t)src * v.CS)[0];
+        eg[q] = (in_a ? geoA : geoB)[src];
+        ec[q] = (in_a ? colA : colB)[src];
       }
     }
+  }
+  if (kWide && last) {
 #pragma unroll
-    for (int q = 0; q < kHalf; ++q) {
-      if (t + (h + q) * 256 < tn) {
-        const int g = epos[h + q];
-        kout[g] = ek[q];
-        jout[g] = ej[q];
-        gout[g] = eg[q];
-        reinterpret_cast<float4*>(cout + (size_t)g * v.CS)[0] = ec[q];
+    for (int q = 0; q < kRadixItems; ++q) {
+      eg[q] = point_geo(v, ej[q]);
+      ec[q] = point_values4(v, ej[q], 0);
+    }
+  }
+  if (last) {
+#pragma unroll
+    for (int q = 0; q < kRadixItems; ++q) {
+      if (t + q * 256 < tn) {
+        const int g = epos[q];
+        keysF[g] = ek[q];
+        perm[g] = ej[q];
+        geo[g] = eg[q];
+        reinterpret_cast<float4*>(col + (size_t)g * v.CS)[0] = ec[q];
+      }
+    }
+  } else {
+    int* kout = out_a ? kA : kB;
+    int* jout = out_a ? vA : vB;
+#pragma unroll
+    for (int q = 0; q < kRadixItems; ++q) {
+      if (t + q * 256 < tn) {
+        kout[epos[q]] = ek[q];
+        jout[epos[q]] = ej[q];
+        if constexpr (!kWide) {
+          (out_a ? geoA : geoB)[epos[q]] = eg[q];
+          (out_a ? colA : colB)[epos[q]] = ec[q];
+        }
       }
     }
   }
   if constexpr (kWide) {  // values beyond the first four (CS <= 32: at most 7 more float4s)
-    constexpr int kExtra = 7;
-    for (int r = 0; r < kRadixItems; ++r) {
-      const int e = t + r * 256;
-      if (e >= tn) continue;
-      const int src = t0 + ssrc[e];
-      const float4* rin = reinterpret_cast<const float4*>(cin + (size_t)src * v.CS);
-      float4 x[kExtra];
+    if (last) {
+      constexpr int kExtra = 7;
+      for (int q = 0; q < kRadixItems; ++q) {
+        if (t + q * 256 >= tn) continue;
+        float4 x[kExtra];
 #pragma unroll
-      for (int q = 0; q < kExtra; ++q) {
-        if (4 * (q + 1) < v.CS) x[q] = first ? point_values4(v, src, 4 * (q + 1)) : rin[q + 1];
+        for (int r = 0; r < kExtra; ++r)
+          if (4 * (r + 1) < v.CS) x[r] = point_values4(v, ej[q], 4 * (r + 1));
+        float4* dst = reinterpret_cast<float4*>(col + (size_t)epos[q] * v.CS);
+#pragma unroll
+        for (int r = 0; r < kExtra; ++r)
+          if (4 * (r + 1) < v.CS) dst[r + 1] = x[r];
       }
-      float4* dst = reinterpret_cast<float4*>(cout + (size_t)epos[r] * v.CS);
-#pragma unroll
-      for (int q = 0; q < kExtra; ++q)
-        if (4 * (q + 1) < v.CS) dst[q + 1] = x[q];
     }
   }
   __syncthreads();
