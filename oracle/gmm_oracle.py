@@ -270,19 +270,21 @@ def _backward_block(args):
         beta = alpha * np.sum(Gi * oi, axis=1)
         cj = val_b[j].astype(np.float64)
         A = alpha * (Gi @ cj) - beta
+        # |A| expanded into its elementary products: alpha sum_k |G c| + |G o|
+        Aabs = alpha * (np.abs(Gi) @ np.abs(cj) + np.sum(np.abs(Gi * oi), axis=1))
         s64 = np.float64(sj)
         dxu = us - np.float64(xj)
         dyv = vs - np.float64(yj)
         d2 = dxu * dxu + dyv * dyv
-        tx = A * w * dxu / (s64 * s64)
-        ty = A * w * dyv / (s64 * s64)
-        ts = A * w * d2 / (s64 ** 3)
-        gpos[t, 0] = math.fsum(tx)
-        gpos[t, 1] = math.fsum(ty)
-        gsig[t] = math.fsum(ts)
-        spos[t, 0] = math.fsum(np.abs(tx))
-        spos[t, 1] = math.fsum(np.abs(ty))
-        ssig[t] = math.fsum(np.abs(ts))
+        fx = w * dxu / (s64 * s64)
+        fy = w * dyv / (s64 * s64)
+        fs = w * d2 / (s64 ** 3)
+        gpos[t, 0] = math.fsum(A * fx)
+        gpos[t, 1] = math.fsum(A * fy)
+        gsig[t] = math.fsum(A * fs)
+        spos[t, 0] = math.fsum(Aabs * np.abs(fx))
+        spos[t, 1] = math.fsum(Aabs * np.abs(fy))
+        ssig[t] = math.fsum(Aabs * fs)
         for k in range(C):
             tc = w * alpha * Gi[:, k]
             gval[t, k] = math.fsum(tc)
@@ -299,7 +301,10 @@ def backward_points(pos, sigma, values, G, H: int, W: int, radius: Optional[floa
     otherwise Z and o are recomputed brute force at every pixel in each
     point's support.  Returns grad_pos [n,2], grad_sigma [n] (the per-point
     derivative, also for a shared sigma), grad_values [n,C] and the matching
-    scales sum_i |term_ij| used by the tolerance.
+    scales used by the tolerance: the sum of the absolute values of the
+    elementary products each gradient expands into (A_ij counted as
+    alpha_i sum_k (|G_ik c_jk| + |G_ik o_ik|), so that a point whose A_ij
+    cancels exactly still has the scale of the float32 terms that cancel).
     """
     pos = np.asarray(pos)
     values = np.asarray(values)

@@ -35,8 +35,9 @@ Readings (also in the design notes):
       dL/dsigma_x = sum_i A_ij w_ij (dx^2 / sigma_x^3 - 1 / sigma_x)   (diagonal;
                    the -1/sigma_x term only when normalised; y likewise)
   with dx = u - x, dy = v - y.  The tolerance scale of a gradient is the sum
-  of the absolute values of its elementary terms (the two terms of a
-  normalised sigma derivative counted separately).
+  of the absolute values of the elementary products it expands into: A_ij as
+  alpha_i sum_k (|G_ik c_jk| + |G_ik o_ik|), and the two terms of a
+  normalised sigma derivative separately.
 
 sigma layouts: isotropic [B, N] or [B]; diagonal [B, N, 2] or [B, 2]
 ((sigma_x, sigma_y) per point or shared).  grad_sigma has sigma's layout
@@ -181,27 +182,25 @@ def backward_variant(pos, sigma, values, G, H: int, W: int, radius: Optional[flo
             Gi = G[b][:, vs, us].T                          # [m, C]
             oi = ob[:, vs, us].T
             beta = alpha * np.sum(Gi * oi, axis=1)
-            A = alpha * (Gi @ values[b, j].astype(np.float64)) - beta
+            cj = values[b, j].astype(np.float64)
+            A = alpha * (Gi @ cj) - beta
+            Aabs = alpha * (np.abs(Gi) @ np.abs(cj) + np.sum(np.abs(Gi * oi), axis=1))
             sx64, sy64 = np.float64(sx), np.float64(sy)
-            tx = A * w * dx / (sx64 * sx64)
-            ty = A * w * dy / (sy64 * sy64)
-            gp[b, j] = (math.fsum(tx), math.fsum(ty))
-            sp[b, j] = (math.fsum(np.abs(tx)), math.fsum(np.abs(ty)))
+            fx = w * dx / (sx64 * sx64)
+            fy = w * dy / (sy64 * sy64)
+            gp[b, j] = (math.fsum(A * fx), math.fsum(A * fy))
+            sp[b, j] = (math.fsum(Aabs * np.abs(fx)), math.fsum(Aabs * np.abs(fy)))
             for k in range(C):
                 tc = w * alpha * Gi[:, k]
                 gv[b, j, k] = math.fsum(tc)
                 sv[b, j, k] = math.fsum(np.abs(tc))
             if diag:
-                parts = [(A * w * dx * dx / sx64 ** 3, A * w / sx64),
-                         (A * w * dy * dy / sy64 ** 3, A * w / sy64)]
-                for a, (t1, t2) in enumerate(parts):
-                    gs[b, j, a] = math.fsum(t1) - (math.fsum(t2) if norm else 0.0)
-                    ss[b, j, a] = math.fsum(np.abs(t1)) + (math.fsum(np.abs(t2)) if norm else 0.0)
+                parts = [(w * dx * dx / sx64 ** 3, w / sx64), (w * dy * dy / sy64 ** 3, w / sy64)]
             else:
-                t1 = A * w * (dx * dx + dy * dy) / sx64 ** 3
-                t2 = 2.0 * A * w / sx64
-                gs[b, j, 0] = math.fsum(t1) - (math.fsum(t2) if norm else 0.0)
-                ss[b, j, 0] = math.fsum(np.abs(t1)) + (math.fsum(np.abs(t2)) if norm else 0.0)
+                parts = [(w * (dx * dx + dy * dy) / sx64 ** 3, 2.0 * w / sx64)]
+            for a, (f1, f2) in enumerate(parts):
+                gs[b, j, a] = math.fsum(A * f1) - (math.fsum(A * f2) if norm else 0.0)
+                ss[b, j, a] = math.fsum(Aabs * f1) + (math.fsum(Aabs * f2) if norm else 0.0)
     if diag:
         if sigma.ndim == 3:
             g_sig, s_sig = gs, ss

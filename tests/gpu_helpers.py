@@ -94,7 +94,14 @@ def check_grad(g_gpu, g_ref, scale, where=""):
     err = np.abs(g_gpu - g_ref)
     lim = GRAD_RTOL * np.maximum(np.abs(g_ref), scale)
     bad = err > lim + 1e-30
-    assert not bad.any(), (f"{where}: {int(bad.sum())}/{bad.size} gradients beyond tolerance; worst "
-                           f"rel {float((err / np.maximum(np.maximum(np.abs(g_ref), scale), 1e-300)).max()):.3g}")
+    if bad.any():
+        idx = np.argwhere(bad)[:6]
+        detail = "; ".join(f"{tuple(int(i) for i in ix)}: gpu {float(g_gpu[tuple(ix)]):.6g} "
+                           f"ref {float(g_ref[tuple(ix)]):.6g} scale {float(scale[tuple(ix)]):.3g}"
+                           for ix in idx)
+        raise AssertionError(
+            f"{where}: {int(bad.sum())}/{bad.size} gradients beyond tolerance; worst rel "
+            f"{float((err / np.maximum(np.maximum(np.abs(g_ref), scale), 1e-300)).max()):.3g}; "
+            f"first: {detail}")
     den = np.maximum(np.maximum(np.abs(g_ref), scale), 1e-300)
     return float((err / den).max()) if err.size else 0.0

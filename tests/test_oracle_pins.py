@@ -458,21 +458,70 @@ def _one_signed_point_case(per_point: bool):
     return pos, sig, val, G, H, W
 
 
+def _sum_log_z(pos, sig, val, H, W):
+    Z = oracle.forward(pos, sig, val, H, W, None)["Z"]
+    return float(np.sum(np.log(Z)))
+
+
 @pytest.mark.parametrize("per_point", [True, False])
-def test_gradient_scales_equal_abs_gradient_when_terms_share_a_sign(per_point):
+def test_gradient_scales_against_log_normaliser_when_terms_share_a_sign(per_point):
+    """Point 0 above-left of the image with the largest value, G = 1, C = 1,
+    no truncation: A_ij = alpha_i (c_0 - o_i) > 0 and its expansion's
+    magnitude is alpha_i (c_0 + o_i), so for every position or sigma
+    derivative scale + grad = 2 c_0 sum_i alpha_i dw_i0 = 2 c_0 d/dtheta
+    sum_i log Z_i, checked by central differences of the pinned Z.  The value
+    gradient's terms w alpha G are all positive: its scale equals it."""
     pos, sig, val, G, H, W = _one_signed_point_case(per_point)
-    r = oracle.backward_points(pos, sig, val, G, H, W, 3.0, 0, [0])
+    r = oracle.backward_points(pos, sig, val, G, H, W, None, 0, [0])
     gp, gs, gv = r["grad_pos"][0], r["grad_sigma"][0], r["grad_values"][0]
     assert np.all(gp > 1e-3) and gs > 1e-3 and np.all(gv > 1e-3)
-    np.testing.assert_allclose(r["scale_pos"][0], gp, rtol=1e-12)
-    assert r["scale_sigma"][0] == pytest.approx(gs, rel=1e-12)
     np.testing.assert_allclose(r["scale_values"][0], gv, rtol=1e-12)
+    c0, h = float(val[0, 0, 0]), 1e-6
+    for a in range(2):
+        p1, p2 = pos.copy(), pos.copy()
+        p1[0, 0, a] += h
+        p2[0, 0, a] -= h
+        fd = (_sum_log_z(p1, sig, val, H, W) - _sum_log_z(p2, sig, val, H, W)) / (2 * h)
+        assert r["scale_pos"][0, a] + gp[a] == pytest.approx(2 * c0 * fd, rel=1e-7)
+    if per_point:
+        s1, s2 = sig.copy(), sig.copy()
+        s1[0, 0] += h
+        s2[0, 0] -= h
+        fd = (_sum_log_z(pos, s1, val, H, W) - _sum_log_z(pos, s2, val, H, W)) / (2 * h)
+        assert r["scale_sigma"][0] + gs == pytest.approx(2 * c0 * fd, rel=1e-7)
     # the same point's gradients flip sign with G while the scales stay
-    rn = oracle.backward_points(pos, sig, val, -G, H, W, 3.0, 0, [0])
+    rn = oracle.backward_points(pos, sig, val, -G, H, W, None, 0, [0])
     np.testing.assert_allclose(rn["grad_pos"][0], -gp, rtol=1e-12)
     np.testing.assert_allclose(rn["scale_pos"][0], r["scale_pos"][0], rtol=1e-12)
     assert rn["scale_sigma"][0] == pytest.approx(r["scale_sigma"][0], rel=1e-12)
     np.testing.assert_allclose(rn["scale_values"][0], r["scale_values"][0], rtol=1e-12)
+
+
+def test_single_point_scales_are_the_cancelled_terms():
+    """One point: out = c wherever Z > 0, so its position and sigma gradients
+    vanish exactly, while the scales keep the size of the float32 terms that
+    cancel: alpha_i w_i = 1 and o_i = c, so scale_x = 2 sum_i |u_i - x| /
+    sigma^2 sum_k |G_ik c_k| and scale_sigma = 2 sum_i d2_i / sigma^3
+    sum_k |G_ik c_k| over the pixels inside the radius (a scalar loop here)."""
+    H, W, x, y, s = 9, 12, 5.3, 3.6, 1.1
+    c = np.array([0.7, -1.9])
+    G = np.random.default_rng(97).standard_normal((1, 2, H, W))
+    r = oracle.backward_points(np.array([[[x, y]]]), np.array([[s]]), c[None, None], G, H, W,
+                               3.0, 0, [0])
+    assert np.all(np.abs(r["grad_pos"]) < 1e-12) and abs(r["grad_sigma"][0]) < 1e-12
+    sx = sy = ss = 0.0
+    rs = float(np.float32(3.0) * np.float32(s))
+    for v in range(H):
+        for u in range(W):
+            d2 = (u - x) ** 2 + (v - y) ** 2
+            if d2 > rs * rs:
+                continue
+            gc = sum(abs(G[0, k, v, u] * c[k]) for k in range(2))
+            sx += 2 * abs(u - x) / s ** 2 * gc
+            sy += 2 * abs(v - y) / s ** 2 * gc
+            ss += 2 * d2 / s ** 3 * gc
+    np.testing.assert_allclose(r["scale_pos"][0], [sx, sy], rtol=1e-12)
+    assert r["scale_sigma"][0] == pytest.approx(ss, rel=1e-12)
 
 
 def test_value_gradient_scale_is_a_partition_of_abs_upstream_gradient():

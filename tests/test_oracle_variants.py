@@ -207,11 +207,12 @@ def test_variant_partition_of_unity_constant_colour_and_scales(kern):
 
 
 @pytest.mark.parametrize("kern", KERNELS)
-def test_variant_scales_equal_the_gradient_where_all_terms_share_a_sign(kern):
-    """A point left of and above the image carrying the largest value, G = 1:
-    A_ij >= 0 and dx, dy > 0 at every pixel it reaches, so each position term
-    (and, unnormalised, each sigma term) is >= 0 and the tolerance scale is
-    exactly |gradient|."""
+def test_variant_scales_against_log_normaliser_when_terms_share_a_sign(kern):
+    """A point left of and above the image carrying the largest value, G = 1,
+    C = 1, no truncation: A_ij = alpha_i (c_0 - o_i) > 0 with expansion
+    magnitude alpha_i (c_0 + o_i), so scale + grad = 2 c_0 d/dtheta sum_i
+    log Z_i for the position (and, unnormalised, the sigmas), checked by
+    central differences of the variant's Z."""
     rng = np.random.default_rng(11)
     B, N, H, W, C = 1, 20, 8, 9, 1
     pos = rng.uniform(1, 8, (B, N, 2))
@@ -221,12 +222,29 @@ def test_variant_scales_equal_the_gradient_where_all_terms_share_a_sign(kern):
     val = rng.uniform(0, 1, (B, N, C))
     val[0, 0] = 2.0
     G = np.ones((B, C, H, W))
-    g = backward_variant(pos, sig, val, G, H, W, 3.0, kern)
-    assert np.all(g["scale_pos"][0, 0] > 0)
-    np.testing.assert_allclose(g["scale_pos"][0, 0], np.abs(g["grad_pos"][0, 0]), rtol=1e-12)
+    g = backward_variant(pos, sig, val, G, H, W, None, kern)
+
+    def slz(p, s):
+        return float(np.sum(np.log(forward_variant(p, s, val, H, W, None, kern)["Z"])))
+
+    h = 1e-6
+    targets = [(pos, (0, 0, a), g["scale_pos"][0, 0, a] + g["grad_pos"][0, 0, a])
+               for a in range(2)]
     if not kern.endswith("_norm"):
-        np.testing.assert_allclose(g["scale_sigma"][0, 0], np.abs(g["grad_sigma"][0, 0]),
-                                   rtol=1e-12)
+        gsig = np.asarray(g["grad_sigma"])[0, 0]
+        ssig = np.asarray(g["scale_sigma"])[0, 0]
+        if diag:
+            targets += [(sig, (0, 0, a), ssig[a] + gsig[a]) for a in range(2)]
+        else:
+            targets += [(sig, (0, 0), ssig + gsig)]
+    for arr, ix, lhs in targets:
+        old = arr[ix]
+        arr[ix] = old + h
+        lp = slz(pos, sig)
+        arr[ix] = old - h
+        lm = slz(pos, sig)
+        arr[ix] = old
+        assert lhs == pytest.approx(2 * 2.0 * (lp - lm) / (2 * h), rel=1e-7), (kern, ix)
 
 
 @pytest.mark.parametrize("kern", ["iso", "diag"])
