@@ -57,6 +57,21 @@ enum {
   INTERP_ENOTFOUND = -5  /* unknown server ticket */
 };
 
+/* Kernel variants (interp_problem.kernel, flags; 0 is the default kernel).
+ *   INTERP_KERNEL_NORMALIZED  each weight keeps the normal density's factor
+ *       1/(2 pi sigma_j^2) (diagonal: 1/(2 pi sigma_xj sigma_yj)), as in Eq. 1
+ *       with the density N(q | mu_j, Sigma_j); with one shared sigma the factor
+ *       cancels and the output equals the default kernel's.
+ *   INTERP_KERNEL_DIAGONAL  axis-aligned anisotropic covariance
+ *       diag(sigma_x^2, sigma_y^2) in place of sigma^2 I:
+ *       w = exp(-(dx^2/sigma_x^2 + dy^2/sigma_y^2) / 2), truncated at
+ *       Mahalanobis radius `radius`, decided in float32 without FMA as
+ *         ix = 1/sigma_x; iy = 1/sigma_y; qx = dx*ix; qy = dy*iy;
+ *         include iff qx*qx + qy*qy <= radius*radius     (each op rounded).
+ *       sigma holds (sigma_x, sigma_y) pairs: [B, N, 2] per point or [B, 2]
+ *       shared; grad_sigma has the same layout. */
+enum { INTERP_KERNEL_NORMALIZED = 1, INTERP_KERNEL_DIAGONAL = 2 };
+
 /* Problem shape.
  *   B      images in the batch (>= 1)
  *   N      points per image (>= 0; N = 0 gives an all-zero output)
@@ -66,12 +81,16 @@ enum {
  *   tile   side in pixels of the square spatial bins used to find near
  *          points: 4, 8, 16, 32 or 64; 0 selects the default 8
  *   sigma_per_point  1: sigma is [B, N]; 0: one shared sigma per image, [B]
+ *          (with INTERP_KERNEL_DIAGONAL: [B, N, 2] and [B, 2])
+ *   kernel 0 or INTERP_KERNEL_* flags (above); C is at most 31 with
+ *          INTERP_KERNEL_NORMALIZED.  The serving path takes kernel 0 only.
  */
 typedef struct interp_problem {
   int32_t B, N, C, H, W;
   float radius;
   int32_t tile;
   int32_t sigma_per_point;
+  int32_t kernel;
 } interp_problem;
 
 /* Bytes of device scratch memory needed by interp_forward / interp_backward

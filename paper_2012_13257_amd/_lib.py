@@ -22,6 +22,7 @@ INTERP_EHIP = -4
 INTERP_ENOTFOUND = -5
 
 NOALLOC_SCRATCH_BYTES = 64 << 20   # INTERP_NOALLOC_SCRATCH_BYTES
+KERNEL_NORMALIZED, KERNEL_DIAGONAL = 1, 2   # INTERP_KERNEL_* flags
 
 QUEUED, RUNNING, DONE, FAILED = 0, 1, 2, 3
 
@@ -33,7 +34,8 @@ c_void_p = ctypes.c_void_p
 
 class InterpProblem(ctypes.Structure):
     _fields_ = [("B", c_int32), ("N", c_int32), ("C", c_int32), ("H", c_int32), ("W", c_int32),
-                ("radius", c_float), ("tile", c_int32), ("sigma_per_point", c_int32)]
+                ("radius", c_float), ("tile", c_int32), ("sigma_per_point", c_int32),
+                ("kernel", c_int32)]
 
 
 class ServerConfig(ctypes.Structure):

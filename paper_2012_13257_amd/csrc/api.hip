@@ -218,6 +218,8 @@ int interp_backward(const interp_problem* prob, const float* pos, const float* s
   if (!out || !grad_out) return fail(INTERP_EINVAL, "out and grad_out must not be NULL");
   if (!aligned(grad_out, 4) || !aligned(out, 4)) return fail(INTERP_EINVAL, "out and grad_out must be 4-byte aligned");
   if (grad_pos && !aligned(grad_pos, 8)) return fail(INTERP_EINVAL, "grad_pos must be 8-byte aligned");
+  if (grad_sigma && g.nsig == 2 && !aligned(grad_sigma, 8))
+    return fail(INTERP_EINVAL, "grad_sigma of a diagonal kernel must be 8-byte aligned");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const ImageView v0 = make_view(g, L, const_cast<void*>(saved), workspace, pos, sigma, values,
                                  const_cast<float*>(out), grad_out, grad_pos, grad_sigma, grad_values);

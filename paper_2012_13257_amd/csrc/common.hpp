@@ -24,7 +24,9 @@ constexpr int kRadixMaxPasses = 4;     // bin keys of up to 32 bits
 inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
 
 // Channel count the kernels are instantiated for: the smallest of
-// {1,2,3,4,8,16,32} that is >= C.  Extra channels are zero padding.
+// {1,2,3,4,8,16,32} that is >= C (C + 1 for a normalised kernel, whose
+// records carry the density factor in the last slot).  Extra channels are
+// zero padding.
 inline int channel_template(int C) {
   if (C <= 4) return C;
   if (C <= 8) return 8;
@@ -79,6 +81,8 @@ struct Geometry {
   int CT, CS, CP;
   float radius;
   int per_point;
+  int kern;                            // INTERP_KERNEL_* flags
+  int nsig;                            // sigma values per point: 1 isotropic, 2 diagonal
   int bx_blocks, by_blocks;            // 8x8 pixel blocks per image row / column
   int npass, dbits, kbits;             // radix sort of the bin keys
   int ntiles;                          // radix tiles per image
@@ -129,7 +133,7 @@ inline Layout make_layout(const Geometry& g) {
   // everything above is all the forward uses; the rest is the backward's
   L.fwd_work_bytes = o;
   L.prec = o;   o = align_up(o + B * HW * size_t(g.CP) * 4);
-  L.gpart = o;  o = align_up(o + B * size_t(g.units256) * 4 + 4);
+  L.gpart = o;  o = align_up(o + B * size_t(g.units256) * 2 * 4 + 8);
   L.work_bytes = o;
   return L;
 }
@@ -143,23 +147,29 @@ inline std::string make_geometry(const interp_problem* p, Geometry* g) {
   if (p->H < 1 || p->W < 1 || p->H > 32768 || p->W > 32768) return "H and W must be in [1, 32768]";
   if (!(p->radius > 0.0f) || !(p->radius <= kMaxRadius)) return "radius must be in (0, 12]";
   if (p->sigma_per_point != 0 && p->sigma_per_point != 1) return "sigma_per_point must be 0 or 1";
+  if (p->kernel < 0 || p->kernel > (INTERP_KERNEL_NORMALIZED | INTERP_KERNEL_DIAGONAL))
+    return "kernel must be a combination of INTERP_KERNEL_NORMALIZED and INTERP_KERNEL_DIAGONAL";
+  const int norm = (p->kernel & INTERP_KERNEL_NORMALIZED) ? 1 : 0;
+  if (p->C + norm > kMaxChannels) return "C must be at most 31 with a normalised kernel";
   const int T = p->tile == 0 ? 8 : p->tile;
   if (T != 4 && T != 8 && T != 16 && T != 32 && T != 64) return "tile must be 0, 4, 8, 16, 32 or 64";
   const long long BN = (long long)p->B * p->N;
   const long long BHW = (long long)p->B * p->H * p->W;
   if (BN >= (1LL << 31)) return "B*N must be below 2^31";
   if (BHW >= (1LL << 31)) return "B*H*W must be below 2^31";
-  if (BN * channel_template(p->C) >= (1LL << 31)) return "B*N*C must be below 2^31";
-  if (BHW * pix_stride(p->C) >= (1LL << 31)) return "B*H*W*(C+1) must be below 2^31";
+  if (BN * channel_template(p->C + norm) >= (1LL << 31)) return "B*N*C must be below 2^31";
+  if (BHW * pix_stride(p->C + norm) >= (1LL << 31)) return "B*H*W*(C+1) must be below 2^31";
   g->B = p->B; g->N = p->N; g->C = p->C; g->H = p->H; g->W = p->W; g->T = T;
   g->nbx = (p->W + T - 1) / T;
   g->nby = (p->H + T - 1) / T;
   g->nb = g->nbx * g->nby;
-  g->CT = channel_template(p->C);
-  g->CS = col_stride(p->C);
-  g->CP = pix_stride(p->C);
+  g->CT = channel_template(p->C + norm);
+  g->CS = col_stride(p->C + norm);
+  g->CP = pix_stride(p->C + norm);
   g->radius = p->radius;
   g->per_point = p->sigma_per_point;
+  g->kern = p->kernel;
+  g->nsig = (p->kernel & INTERP_KERNEL_DIAGONAL) ? 2 : 1;
   g->bx_blocks = (p->W + kBlockSide - 1) / kBlockSide;
   g->by_blocks = (p->H + kBlockSide - 1) / kBlockSide;
   radix_plan(g->nb, &g->npass, &g->dbits, &g->kbits);
@@ -175,17 +185,20 @@ inline std::string make_geometry(const interp_problem* p, Geometry* g) {
 // The view of image 0 plus image_of() gives every image of a batch.
 struct ImageView {
   int N, C, H, W, T, nbx, nby, nb, CS, CP, per_point;
+  int kern, nsig;           // kernel flags; sigma values per point (1 or 2)
+  int zslot;                // normalised: record slot of the density factor, else -1
+  float r2;                 // f32(radius * radius): the diagonal kernel's test
   int npass, dbits, kbits, ntiles, units256;
   int bx_blocks, by_blocks;
   float radius, inv_tile;
   // inputs / outputs
   const float2* pos;        // [N]
-  const float* sigma;       // per point: [N]; shared: the image's one value
+  const float* sigma;       // per point: [N, nsig]; shared: the image's nsig values
   const float* values;      // [N, C]
   float* out;               // [C, H, W]
   const float* grad_out;    // [C, H, W]
   float* grad_pos;          // [N, 2] or null
-  float* grad_sigma;        // per point [N]; shared: the image's one value; or null
+  float* grad_sigma;        // like sigma, or null
   float* grad_values;       // [N, C] or null
   // saved state
   float* Z;                 // [H, W]
@@ -204,7 +217,7 @@ struct ImageView {
   int* dtot;                // [256] per-digit totals of the current radix pass
   float* rpart;             // [units256] partial maxima of radius*sigma
   float* prec;              // [H, W, CP] backward pixel records
-  float* gpart;             // [units256] partial sums of dL/dsigma (shared sigma)
+  float* gpart;             // [units256, 2] partial sums of dL/dsigma (shared sigma)
 };
 
 template <typename T>
@@ -216,12 +229,12 @@ __host__ __device__ inline ImageView image_of(const ImageView& v0, int b) {
   ImageView v = v0;
   const size_t bb = b, N = v0.N, HW = size_t(v0.H) * v0.W;
   v.pos = shift(v0.pos, bb * N);
-  v.sigma = shift(v0.sigma, v0.per_point ? bb * N : bb);
+  v.sigma = shift(v0.sigma, (v0.per_point ? bb * N : bb) * v0.nsig);
   v.values = shift(v0.values, bb * N * v0.C);
   v.out = shift(v0.out, bb * v0.C * HW);
   v.grad_out = shift(v0.grad_out, bb * v0.C * HW);
   v.grad_pos = shift(v0.grad_pos, bb * N * 2);
-  v.grad_sigma = shift(v0.grad_sigma, v0.per_point ? bb * N : bb);
+  v.grad_sigma = shift(v0.grad_sigma, (v0.per_point ? bb * N : bb) * v0.nsig);
   v.grad_values = shift(v0.grad_values, bb * N * v0.C);
   v.Z = shift(v0.Z, bb * HW);
   v.reach = shift(v0.reach, bb);
@@ -243,7 +256,7 @@ __host__ __device__ inline ImageView image_of(const ImageView& v0, int b) {
   v.dtot = shift(v0.dtot, bb * 256);
   v.rpart = shift(v0.rpart, bb * v0.units256);
   v.prec = shift(v0.prec, bb * HW * v0.CP);
-  v.gpart = shift(v0.gpart, bb * v0.units256);
+  v.gpart = shift(v0.gpart, bb * v0.units256 * 2);
   return v;
 }
 
@@ -257,6 +270,9 @@ inline ImageView make_view(const Geometry& g, const Layout& L, void* saved, void
   ImageView v;
   v.N = g.N; v.C = g.C; v.H = g.H; v.W = g.W; v.T = g.T; v.nbx = g.nbx; v.nby = g.nby; v.nb = g.nb;
   v.CS = g.CS; v.CP = g.CP; v.per_point = g.per_point;
+  v.kern = g.kern; v.nsig = g.nsig;
+  v.zslot = (g.kern & INTERP_KERNEL_NORMALIZED) ? g.CT - 1 : -1;
+  v.r2 = g.radius * g.radius;  // one rounded float multiply, as the test specifies
   v.npass = g.npass; v.dbits = g.dbits; v.kbits = g.kbits; v.ntiles = g.ntiles;
   v.units256 = g.units256;
   v.bx_blocks = g.bx_blocks; v.by_blocks = g.by_blocks;

@@ -48,17 +48,34 @@ __device__ inline int bin_coord(float c, float inv_tile, int nmax) {
   return (int)f;
 }
 
-__device__ inline float sigma_of(const ImageView& v, int j) {
-  return v.per_point ? v.sigma[j] : v.sigma[0];
+// (sigma_x, sigma_y) of point j: the isotropic kernel's sigma twice, or the
+// diagonal kernel's pair.
+__device__ inline float2 sigma2_of(const ImageView& v, int j) {
+  const float* s = v.per_point ? v.sigma + (size_t)j * v.nsig : v.sigma;
+  return v.nsig == 2 ? make_float2(s[0], s[1]) : make_float2(s[0], s[0]);
 }
 
-// The sorted point record: x, y, exp2 scale k = -log2(e)/(2 sigma^2) and the
-// squared radius R2 = f32(f32(radius*sigma)^2) of the radius test.
-__device__ inline float4 make_geo(float2 p, float sg, float radius) {
-  const float rs = __fmul_rn(radius, sg);
+// The sorted point record.  Isotropic kernel: x, y, the exp2 scale
+// k = -log2(e)/(2 sigma^2) and the squared radius R2 = f32(f32(radius*sigma)^2)
+// of the radius test.  Diagonal kernel: x, y and the inverse sigmas
+// ix = 1/sigma_x, iy = 1/sigma_y of the Mahalanobis test (correctly rounded
+// divisions, as the test specifies).
+__device__ inline float4 make_geo(float2 p, float2 sg, float radius, bool diag) {
+  if (diag) return make_float4(p.x, p.y, __fdiv_rn(1.0f, sg.x), __fdiv_rn(1.0f, sg.y));
+  const float rs = __fmul_rn(radius, sg.x);
   const float R2 = __fmul_rn(rs, rs);
-  const float kk = -0.5f * kLog2e / __fmul_rn(sg, sg);
+  const float kk = -0.5f * kLog2e / __fmul_rn(sg.x, sg.x);
   return make_float4(p.x, p.y, kk, R2);
+}
+
+// The normal density's factor 1/(2 pi sigma_x sigma_y) of a normalised kernel.
+__device__ inline float density_factor(float2 sg) {
+  return 1.0f / (6.28318530717958648f * sg.x * sg.y);
+}
+
+// Truncation radius (pixels) of a point along its longer axis.
+__device__ inline float point_reach(float2 sg, float radius) {
+  return __fmul_rn(radius, fmaxf(sg.x, sg.y));
 }
 
 // Conservative reach (pixels) of a point set whose largest radius*sigma is
@@ -95,18 +112,22 @@ __device__ inline void wave_lds_sync() {
 // Binning: stable LSD radix sort of the bin keys (no global atomics)
 // ---------------------------------------------------------------------------
 
-// The record of point j: geo (x, y, k, R2) and its values padded to CS.
+// The record of point j: geo (make_geo) and its values padded to CS; a
+// normalised kernel's records carry the density factor in slot zslot.
 __device__ inline float4 point_geo(const ImageView& v, int j) {
-  return make_geo(v.pos[j], sigma_of(v, j), v.radius);
+  return make_geo(v.pos[j], sigma2_of(v, j), v.radius, v.nsig == 2);
 }
 __device__ inline float4 point_values4(const ImageView& v, int j, int c) {
   const float* src = v.values + (size_t)j * v.C;
-  float4 q;
-  q.x = c < v.C ? src[c] : 0.0f;
-  q.y = c + 1 < v.C ? src[c + 1] : 0.0f;
-  q.z = c + 2 < v.C ? src[c + 2] : 0.0f;
-  q.w = c + 3 < v.C ? src[c + 3] : 0.0f;
-  return q;
+  float q[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) q[i] = c + i < v.C ? src[c + i] : 0.0f;
+  if (v.zslot >= c && v.zslot < c + 4) {
+    const float z = density_factor(sigma2_of(v, j));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) q[i] = c + i == v.zslot ? z : q[i];
+  }
+  return make_float4(q[0], q[1], q[2], q[3]);
 }
 
 // unit = one radix tile of kRadixTile points: bin key of every point, the
@@ -119,13 +140,12 @@ __device__ inline void bin_keys(const ImageView& v, int tile, float* red4, int* 
   const int width0 = v.npass > 0 ? min(v.dbits, v.kbits) : 0;
   const int mask0 = (1 << width0) - 1;
   const int j0 = tile * kRadixTile + t;
-  float2 p[kRadixItems];
-  float sg[kRadixItems];
+  float2 p[kRadixItems], sg[kRadixItems];
 #pragma unroll
   for (int r = 0; r < kRadixItems; ++r) {
     const int jc = min(j0 + r * 256, v.N - 1);  // clamped: no load behind a branch
     p[r] = v.pos[jc];
-    sg[r] = sigma_of(v, jc);
+    sg[r] = sigma2_of(v, jc);
   }
   lh[t] = 0;
   __syncthreads();
@@ -138,7 +158,7 @@ __device__ inline void bin_keys(const ImageView& v, int tile, float* red4, int* 
           bin_coord(p[r].y, v.inv_tile, v.nby) * v.nbx + bin_coord(p[r].x, v.inv_tile, v.nbx);
       v.binof[j] = key;
       if (v.npass > 0) atomicAdd(&lh[key & mask0], 1);
-      float rs = __fmul_rn(v.radius, sg[r]);
+      float rs = point_reach(sg[r], v.radius);
       if (!(rs >= 0.0f)) rs = 0.0f;  // caller contract violated; keep the reach sane
       rmax = fmaxf(rmax, rs);
     }
@@ -149,7 +169,7 @@ __device__ inline void bin_keys(const ImageView& v, int tile, float* red4, int* 
       if (j >= v.N) continue;
       v.keysF[j] = 0;
       v.perm[j] = j;
-      v.geo[j] = make_geo(p[r], sg[r], v.radius);
+      v.geo[j] = make_geo(p[r], sg[r], v.radius, v.nsig == 2);
       float4* dst = reinterpret_cast<float4*>(v.col + (size_t)j * v.CS);
       for (int c = 0; c < v.CS; c += 4) dst[c / 4] = point_values4(v, j, c);
     }
@@ -434,6 +454,47 @@ __host__ __device__ inline int finish_units(int N) { return (N + 1 + 255) / 256;
 // Forward gather
 // ---------------------------------------------------------------------------
 
+// Kernel variants (template parameter KV: INTERP_KERNEL_* flags).
+template <int KV> constexpr bool kDiagonal = (KV & INTERP_KERNEL_DIAGONAL) != 0;
+template <int KV> constexpr bool kNormalized = (KV & INTERP_KERNEL_NORMALIZED) != 0;
+constexpr float kHalfLog2e = -0.5f * kLog2e;  // exp(-m/2) = exp2(m * kHalfLog2e)
+
+// The weight of pixel (fu, fv) for sorted record r, zero outside the
+// truncation radius: the specified float32 test, every operation rounded.
+// Isotropic: d2 = dx*dx + dy*dy, include iff d2 <= R2, w = exp2(d2 * k).
+// Diagonal: qx = dx*ix, qy = dy*iy, m2 = qx*qx + qy*qy, include iff
+// m2 <= r2, w = exp2(m2 * (-log2(e)/2)).
+template <int KV>
+__device__ inline float pair_weight(float fu, float fv, float4 r, float r2) {
+  const float dx = fu - r.x;
+  const float dy = fv - r.y;
+  if constexpr (kDiagonal<KV>) {
+    const float qx = dx * r.z;
+    const float qy = dy * r.w;
+    const float m2 = qx * qx + qy * qy;
+    const float w = __builtin_amdgcn_exp2f(m2 * kHalfLog2e);
+    return (m2 <= r2) ? w : 0.0f;
+  } else {
+    const float d2 = dx * dx + dy * dy;
+    const float w = __builtin_amdgcn_exp2f(d2 * r.z);
+    return (d2 <= r.w) ? w : 0.0f;
+  }
+}
+
+// Conservative test: can record g reach a box whose nearest point is ex, ey
+// (>= 0) away from it along x and y?
+template <int KV>
+__device__ inline float box_sq(float e, float inv) {
+  if constexpr (kDiagonal<KV>) { const float a = e * inv; return a * a; }
+  else return e * e;
+}
+template <int KV>
+__device__ inline float reach_lim(float4 g, float r2) {
+  if constexpr (kDiagonal<KV>) return r2 * 1.001f + 1e-6f;
+  else return g.w * 1.001f + 1e-6f;
+}
+
+
 __host__ __device__ inline int fwd_tiles_x(int bx_blocks) { return (bx_blocks + 1) / 2; }
 __host__ __device__ inline int fwd_tiles(int bx_blocks, int by_blocks) {
   return ((bx_blocks + 1) / 2) * ((by_blocks + 1) / 2);
@@ -445,10 +506,12 @@ __host__ __device__ inline int fwd_tiles(int bx_blocks, int by_blocks) {
 // bin row), taken 64 at a time: each lane tests one candidate's disk against
 // the block, the hits are compacted in candidate order into the wavefront's
 // LDS list, and every lane then evaluates each hit for its pixel.
-template <int CT>
+template <int CT, int KV = 0>
 __device__ inline void forward_tile(const ImageView& v, int tile, float4* s_geo /*[4][64]*/,
                                     float4* s_col /*[4][64*CS/4]*/) {
   constexpr int CS = CT < 4 ? 4 : CT;
+  constexpr int NC = kNormalized<KV> ? CT - 1 : CT;  // channel slots (the last is the factor)
+  const float r2 = v.r2;
   const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wgx = fwd_tiles_x(v.bx_blocks);
   const int ty = tile / wgx, tx = tile - ty * wgx;
@@ -489,7 +552,7 @@ __device__ inline void forward_tile(const ImageView& v, int tile, float4* s_geo 
         g = gb[jc];
         const float ex = fmaxf(fmaxf((float)u0 - g.x, g.x - (float)ue), 0.0f);
         const float ey = fmaxf(fmaxf((float)v0 - g.y, g.y - (float)ve), 0.0f);
-        hit = ex * ex + ey * ey <= g.w * 1.001f + 1e-6f;
+        hit = box_sq<KV>(ex, g.z) + box_sq<KV>(ey, g.w) <= reach_lim<KV>(g, r2);
       }
       const unsigned long long mask = __ballot(hit);
       if (mask == 0) continue;
@@ -511,15 +574,11 @@ __device__ inline void forward_tile(const ImageView& v, int tile, float4* s_geo 
           const float4 tq = lcol[i * (CS / 4) + q];
           cc[4 * q] = tq.x; cc[4 * q + 1] = tq.y; cc[4 * q + 2] = tq.z; cc[4 * q + 3] = tq.w;
         }
-        // radius test exactly as specified: float32, every operation rounded
-        const float dx = fu - r.x;
-        const float dy = fv - r.y;
-        const float d2 = dx * dx + dy * dy;
-        float w = __builtin_amdgcn_exp2f(d2 * r.z);
-        w = (d2 <= r.w) ? w : 0.0f;
+        float w = pair_weight<KV>(fu, fv, r, r2);
+        if constexpr (kNormalized<KV>) w *= cc[CT - 1];
         Z += w;
 #pragma unroll
-        for (int k = 0; k < CT; ++k) acc[k] = __builtin_fmaf(w, cc[k], acc[k]);
+        for (int k = 0; k < NC; ++k) acc[k] = __builtin_fmaf(w, cc[k], acc[k]);
       }
       wave_lds_sync();
     }
@@ -529,7 +588,7 @@ __device__ inline void forward_tile(const ImageView& v, int tile, float4* s_geo 
     const size_t HW = (size_t)v.H * v.W;
     const size_t pix = (size_t)vv * v.W + u;
 #pragma unroll
-    for (int k = 0; k < CT; ++k) {
+    for (int k = 0; k < NC; ++k) {
       if (k < v.C) v.out[k * HW + pix] = Z > 0.0f ? acc[k] / Z : 0.0f;
     }
     v.Z[pix] = Z;
@@ -545,7 +604,8 @@ __device__ inline void forward_tile(const ImageView& v, int tile, float4* s_geo 
 // the LDS list of each quarter its disk reaches, and a quarter's list is
 // evaluated four candidates at a time -- lane group g = lane / 16 takes list
 // entries g, g+4, ... for pixel lane % 16 of the quarter (lists are padded to
-// a multiple of four with a null record: w = 0, values 0).  The next chunk's
+// a multiple of four with a null record that fails the radius test: w = 0,
+// values 0).  The next chunk's
 // records are loaded while the current one is processed.  Partial sums are
 // combined in a fixed order: the lane groups of a quarter as (g0 + g1) +
 // (g2 + g3), then the two wavefronts of a block (if split) in order.
@@ -613,9 +673,11 @@ __device__ inline bool unit_is_heavy(const int cost[4]) {
 
 // mode 0: the whole unit, wavefront w on block w; mode 1 / 2: blocks 0-1 /
 // 2-3, wavefronts 2b and 2b+1 on the b-th of them.
-template <int CT>
+template <int CT, int KV = 0>
 __device__ inline void forward_block_q(const ImageView& v, int unit, int mode, float4* s_rec) {
   static_assert(CT <= 4, "the quarter lists hold the values of a record in one float4");
+  constexpr int NC = kNormalized<KV> ? CT - 1 : CT;  // channel slots (the last is the factor)
+  const float r2 = v.r2;
   const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int grp = lane >> 4, p = lane & 15;
   const int split = mode == 0 ? 1 : 2;                         // wavefronts per block
@@ -654,7 +716,9 @@ __device__ inline void forward_block_q(const ImageView& v, int unit, int mode, f
   }
 
   float4* lst = s_rec + wid * (4 * kQuarterList * 2);
-  const float4 null_geo = make_float4(0.0f, 0.0f, 0.0f, -1.0f);
+  // the padding record fails every kernel's radius test: its NaN position
+  // makes d2 (or m2) NaN, and NaN <= anything is false (w = 0)
+  const float4 null_geo = make_float4(__builtin_nanf(""), __builtin_nanf(""), 0.0f, -1.0f);
   const float4 zero4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 
   // bin rows in groups of 64 (one row per lane)
@@ -701,12 +765,13 @@ __device__ inline void forward_block_q(const ImageView& v, int unit, int mode, f
       }
       cur = nxt;
       // disk of the candidate against the box of each quarter (conservative)
-      const float lim = g.w * 1.001f + 1e-6f;
+      const float lim = reach_lim<KV>(g, r2);
       const float exl = fmaxf(fmaxf(fu0 - g.x, g.x - ful), 0.0f);
       const float exr = fmaxf(fmaxf(fur0 - g.x, g.x - fure), 0.0f);
       const float eyt = fmaxf(fmaxf(fv0 - g.y, g.y - fvt), 0.0f);
       const float eyb = fmaxf(fmaxf(fvb0 - g.y, g.y - fvbe), 0.0f);
-      const float xl = exl * exl, xr = exr * exr, yt = eyt * eyt, yb = eyb * eyb;
+      const float xl = box_sq<KV>(exl, g.z), xr = box_sq<KV>(exr, g.z);
+      const float yt = box_sq<KV>(eyt, g.w), yb = box_sq<KV>(eyb, g.w);
       const bool h[4] = {in && xl + yt <= lim, in && has_r && xr + yt <= lim,
                          in && has_b && xl + yb <= lim, in && has_r && has_b && xr + yb <= lim};
       unsigned long long m[4];
@@ -743,16 +808,12 @@ __device__ inline void forward_block_q(const ImageView& v, int unit, int mode, f
         for (int i = 0; i < nit[q]; ++i) {
           const float4 r = L[8 * i];
           const float4 cv = L[8 * i + 1];
-          // radius test exactly as specified: float32, every operation rounded
-          const float dx = fu - r.x;
-          const float dy = fv - r.y;
-          const float d2 = dx * dx + dy * dy;
-          float w = __builtin_amdgcn_exp2f(d2 * r.z);
-          w = (d2 <= r.w) ? w : 0.0f;
-          Z[q] += w;
           const float cc[4] = {cv.x, cv.y, cv.z, cv.w};
+          float w = pair_weight<KV>(fu, fv, r, r2);
+          if constexpr (kNormalized<KV>) w *= cc[CT - 1];
+          Z[q] += w;
 #pragma unroll
-          for (int k = 0; k < CT; ++k) acc[q][k] = __builtin_fmaf(w, cc[k], acc[q][k]);
+          for (int k = 0; k < NC; ++k) acc[q][k] = __builtin_fmaf(w, cc[k], acc[q][k]);
         }
       }
       wave_lds_sync();
@@ -855,10 +916,12 @@ constexpr int kBwdGroup = 4;
 // computes it, and the shared-sigma partial sum is taken in the original
 // point order: the output is deterministic.  lds: 256 + 32 ints; stage:
 // kBwdStageF4 float4s.
-template <int CT>
+template <int CT, int KV = 0>
 __device__ inline void bwd_point(const ImageView& v, int unit, float* red4, int* lds,
                                  float4* stage) {
   constexpr int CS = CT < 4 ? 4 : CT;
+  constexpr bool kD = kDiagonal<KV>, kN = kNormalized<KV>;
+  constexpr int NC = kN ? CT - 1 : CT;  // channel slots (the last is the density factor)
   constexpr int CP = (CT + 1 + 3) / 4 * 4;
   constexpr int CP4 = CP / 4;
   int* order = lds;            // [256] local point index by regrouped slot
@@ -900,7 +963,8 @@ __device__ inline void bwd_point(const ImageView& v, int unit, float* red4, int*
     int cls = 0;
     if (tt < v.N) {
       const float4 gg = v.geo[tt];
-      cls = min(31, 1 + (int)fminf(2.0f * sqrtf(fmaxf(gg.w, 0.0f)), 30.0f));
+      const float ext = kD ? v.radius / fmaxf(fminf(gg.z, gg.w), 1e-30f) : sqrtf(fmaxf(gg.w, 0.0f));
+      cls = min(31, 1 + (int)fminf(2.0f * ext, 30.0f));
     }
     if (threadIdx.x < 32) cls_n[threadIdx.x] = 0;
     __syncthreads();
@@ -916,19 +980,19 @@ __device__ inline void bwd_point(const ImageView& v, int unit, float* red4, int*
   }
   const int lp = order[threadIdx.x];
   const int t = base + lp;
-  float gsig = 0.0f;
+  float gsig = 0.0f, gsig2 = 0.0f;
   if (t < v.N) {
     const float4 g = v.geo[t];
     float cc[CT];
 #pragma unroll
     for (int k = 0; k < CT; ++k) cc[k] = v.col[(size_t)t * CS + k];
+    const float zeta = kN ? cc[CT - 1] : 1.0f;
     const int j = v.perm[t];
-    const float sg = sigma_of(v, j);
-    const float Rh = conservative_reach(__fmul_rn(v.radius, sg));
-    // bounding box of the disk, clipped to the image (the float clamps also
-    // drop NaN and keep the conversions in range)
-    const float fulo = fminf(fmaxf(ceilf(g.x - Rh), 0.0f), (float)v.W);
-    const float fuhi = fmaxf(fminf(floorf(g.x + Rh), (float)(v.W - 1)), -1.0f);
+    const float2 sg = sigma2_of(v, j);
+    const float Rhx = conservative_reach(__fmul_rn(v.radius, sg.x));
+    const float Rh = conservative_reach(__fmul_rn(v.radius, sg.y));  // along y
+    // bounding box of the disk (ellipse), clipped to the image (the float
+    // clamps also drop NaN and keep the conversions in range)
     const float fvlo = fminf(fmaxf(ceilf(g.y - Rh), 0.0f), (float)v.H);
     const float fvhi = fmaxf(fminf(floorf(g.y + Rh), (float)(v.H - 1)), -1.0f);
     int vlo = (int)fvlo, vhi = (int)fvhi;
@@ -936,18 +1000,19 @@ __device__ inline void bwd_point(const ImageView& v, int unit, float* red4, int*
       vlo = max(vlo, ry0);
       vhi = min(vhi, ry1);
     }
-    float gx = 0.0f, gy = 0.0f, gs = 0.0f;
-    float gc[CT];
+    float gx = 0.0f, gy = 0.0f, gs = 0.0f, gs2 = 0.0f, ga = 0.0f;
+    float gc[NC];
 #pragma unroll
-    for (int k = 0; k < CT; ++k) gc[k] = 0.0f;
-    const float R2m = g.w * (1.0f + 0x1p-20f);
+    for (int k = 0; k < NC; ++k) gc[k] = 0.0f;
+    // squared radius of the chord computation, a little beyond the test's
+    const float R2m = (kD ? v.r2 : g.w) * (1.0f + 0x1p-20f);
     // the disk walk; rec(py, px, q) returns float4 q of pixel (py, px)'s record
     // interior: the disk's box, widened by G - 1 pixels for the groups of G,
     // lies inside the image (and the staged window) for every lane of the
     // wavefront, so the rows need no clamping
     constexpr int G = kBwdGroup;
-    const bool interior_lane = !(t < v.N) || (g.x - Rh >= (float)max(rx0 * staged, 0) &&
-                                              g.x + Rh + (float)(G - 1) <=
+    const bool interior_lane = !(t < v.N) || (g.x - Rhx >= (float)max(rx0 * staged, 0) &&
+                                              g.x + Rhx + (float)(G - 1) <=
                                                   (float)(staged ? rx1 : v.W - 1) &&
                                               g.y - Rh >= 0.0f && g.y + Rh <= (float)(v.H - 1));
     const bool interior = __ballot(!interior_lane) == 0;
@@ -955,13 +1020,15 @@ __device__ inline void bwd_point(const ImageView& v, int unit, float* red4, int*
       constexpr bool kInterior = decltype(interior_tag)::value;
       for (int py = vlo; py <= vhi; ++py) {
         const float dy = (float)py - g.y;
-        const float dyy = dy * dy;
+        // the row's term of the test: dy^2, or qy^2 = (dy / sigma_y)^2
+        const float qy = kD ? dy * g.w : dy;
+        const float dyy = qy * qy;
         // conservative chord of the disk on this row (v_sqrt_f32's error is
         // far inside the margin), widened to a multiple of G pixels inside the
         // image so that every row runs whole groups; every pixel is visited
         // without branching (pixels outside the radius get w = 0)
-        const float rr =
-            __builtin_amdgcn_sqrtf(fmaxf(R2m - dyy, 0.0f)) * (1.0f + 0x1p-10f) + 0x1p-10f;
+        const float rr = __builtin_amdgcn_sqrtf(fmaxf(R2m - dyy, 0.0f)) * (kD ? sg.x : 1.0f) *
+                             (1.0f + 0x1p-10f) + 0x1p-10f;
         int ulo, uhi;
         if constexpr (kInterior) {
           ulo = (int)ceilf(g.x - rr);
@@ -974,25 +1041,34 @@ __device__ inline void bwd_point(const ImageView& v, int unit, float* red4, int*
         // columns stay far below 2^24), so no conversion per pixel
         auto pixel = [&](int px, float fpx) {
           const float dx = fpx - g.x;
-          const float d2 = dx * dx + dyy;
+          // the forward's test and weight, bit for bit (pair_weight)
+          const float qx = kD ? dx * g.z : dx;
+          const float qxx = qx * qx;
+          const float d2 = qxx + dyy;
           float rec[CP];
 #pragma unroll
           for (int q = 0; q < CP4; ++q) {
             const float4 r4 = rec_of(py, px, q);
             rec[4 * q] = r4.x; rec[4 * q + 1] = r4.y; rec[4 * q + 2] = r4.z; rec[4 * q + 3] = r4.w;
           }
-          float w = __builtin_amdgcn_exp2f(d2 * g.z);
-          w = (d2 <= g.w) ? w : 0.0f;
+          float w = __builtin_amdgcn_exp2f(d2 * (kD ? kHalfLog2e : g.z));
+          w = (d2 <= (kD ? v.r2 : g.w)) ? w : 0.0f;
+          if constexpr (kN) w *= zeta;
           float A = -rec[CT];
 #pragma unroll
-          for (int k = 0; k < CT; ++k) {
-            A = __builtin_fmaf(rec[k], cc[k], A);
-            gc[k] = __builtin_fmaf(w, rec[k], gc[k]);
-          }
+          for (int k = 0; k < CT; ++k) A = __builtin_fmaf(rec[k], cc[k], A);
+#pragma unroll
+          for (int k = 0; k < NC; ++k) gc[k] = __builtin_fmaf(w, rec[k], gc[k]);
           const float tA = A * w;
-          gx = __builtin_fmaf(tA, dx, gx);
-          gy = __builtin_fmaf(tA, dy, gy);
-          gs = __builtin_fmaf(tA, d2, gs);
+          gx = __builtin_fmaf(tA, qx, gx);
+          gy = __builtin_fmaf(tA, qy, gy);
+          if constexpr (kD) {
+            gs = __builtin_fmaf(tA, qxx, gs);
+            gs2 = __builtin_fmaf(tA, dyy, gs2);
+          } else {
+            gs = __builtin_fmaf(tA, d2, gs);
+          }
+          if constexpr (kN) ga += tA;
         };
         auto groups = [&](int lo, int n) {  // n: a multiple of G
           float fpx = (float)lo;
@@ -1033,31 +1109,57 @@ __device__ inline void bwd_point(const ImageView& v, int unit, float* red4, int*
     } else {
       if (interior) walk(from_global, Yes{}); else walk(from_global, No{});
     }
-    const float inv_s2 = 1.0f / (sg * sg);
-    if (v.grad_pos) reinterpret_cast<float2*>(v.grad_pos)[j] = make_float2(gx * inv_s2, gy * inv_s2);
-    gsig = gs * inv_s2 / sg;
-    if (v.grad_sigma && v.per_point) v.grad_sigma[j] = gsig;
+    // chain rule through the weight: d w / d x = w dx / sigma^2 (isotropic)
+    // or w qx / sigma_x (diagonal); d w / d sigma = w d2 / sigma^3 or
+    // w qx^2 / sigma_x; a normalised kernel's factor adds -2 w / sigma or
+    // -w / sigma_x
+    float2 gp;
+    if constexpr (kD) {
+      gp = make_float2(gx * g.z, gy * g.w);
+      gsig = (kN ? gs - ga : gs) * g.z;
+      gsig2 = (kN ? gs2 - ga : gs2) * g.w;
+    } else {
+      const float inv_s2 = 1.0f / (sg.x * sg.x);
+      gp = make_float2(gx * inv_s2, gy * inv_s2);
+      gsig = gs * inv_s2 / sg.x;
+      if constexpr (kN) gsig -= 2.0f * ga / sg.x;
+    }
+    if (v.grad_pos) reinterpret_cast<float2*>(v.grad_pos)[j] = gp;
+    if (v.grad_sigma && v.per_point) {
+      if constexpr (kD) reinterpret_cast<float2*>(v.grad_sigma)[j] = make_float2(gsig, gsig2);
+      else v.grad_sigma[j] = gsig;
+    }
     if (v.grad_values) {
 #pragma unroll
-      for (int k = 0; k < CT; ++k)
+      for (int k = 0; k < NC; ++k)
         if (k < v.C) v.grad_values[(size_t)j * v.C + k] = gc[k];
     }
   }
   if (!v.per_point && v.grad_sigma) {
+    // the shared sigma's derivative: per-unit partial sums in point order
     __syncthreads();
     gs_l[lp] = gsig;
     __syncthreads();
     const float s = block_sum(gs_l[threadIdx.x], red4);
-    if (threadIdx.x == 0) v.gpart[unit] = s;
+    if (threadIdx.x == 0) v.gpart[2 * unit] = s;
+    if constexpr (kD) {
+      gs_l[lp] = gsig2;
+      __syncthreads();
+      const float s2 = block_sum(gs_l[threadIdx.x], red4);
+      if (threadIdx.x == 0) v.gpart[2 * unit + 1] = s2;
+    }
   }
 }
 
 // one 256-thread block per image: grad_sigma = fixed-order sum of gpart
+// (one value per sigma component)
 __device__ inline void bwd_sigma_sum(const ImageView& v, float* red4) {
-  float s = 0.0f;
-  for (int q = threadIdx.x; q < v.units256; q += 256) s += v.gpart[q];
-  s = block_sum(s, red4);
-  if (threadIdx.x == 0) v.grad_sigma[0] = s;
+  for (int a = 0; a < v.nsig; ++a) {
+    float s = 0.0f;
+    for (int q = threadIdx.x; q < v.units256; q += 256) s += v.gpart[2 * q + a];
+    s = block_sum(s, red4);
+    if (threadIdx.x == 0) v.grad_sigma[a] = s;
+  }
 }
 
 }  // namespace dev

@@ -25,22 +25,25 @@ DEFAULT_TILE = 8
 
 
 def problem(pos: torch.Tensor, sigma: torch.Tensor, values: torch.Tensor, H: int, W: int,
-            radius: float = 3.0, tile: int = DEFAULT_TILE) -> _lib.InterpProblem:
+            radius: float = 3.0, tile: int = DEFAULT_TILE, normalized: bool = False,
+            anisotropic: bool = False) -> _lib.InterpProblem:
+    """The C-ABI problem descriptor of these tensors.  normalized keeps the
+    density factor in each weight; anisotropic takes a diagonal covariance,
+    sigma then holding (sigma_x, sigma_y) pairs: [B, N, 2] or [B, 2]."""
     if pos.dim() != 3 or pos.shape[2] != 2:
         raise ValueError("pos must be [B, N, 2]")
     B, N = int(pos.shape[0]), int(pos.shape[1])
     if values.dim() != 3 or values.shape[0] != B or values.shape[1] != N:
         raise ValueError("values must be [B, N, C]")
-    if sigma.dim() == 2:
-        if tuple(sigma.shape) != (B, N):
-            raise ValueError("per-point sigma must be [B, N]")
+    k = 2 if anisotropic else 1
+    tail = (2,) if anisotropic else ()
+    if tuple(sigma.shape) == (B, N) + tail:
         per_point = 1
-    elif sigma.dim() == 1:
-        if sigma.shape[0] != B:
-            raise ValueError("shared sigma must be [B]")
+    elif tuple(sigma.shape) == (B,) + tail:
         per_point = 0
     else:
-        raise ValueError("sigma must be [B, N] or [B]")
+        raise ValueError("sigma must be [B, N] or [B]" if k == 1 else
+                         "anisotropic sigma must be [B, N, 2] or [B, 2]")
     for name, t in (("pos", pos), ("sigma", sigma), ("values", values)):
         if t.dtype != torch.float32:
             raise ValueError(f"{name} must be float32")
@@ -48,8 +51,9 @@ def problem(pos: torch.Tensor, sigma: torch.Tensor, values: torch.Tensor, H: int
             raise ValueError(f"{name} must be on the ROCm device")
         if not t.is_contiguous():
             raise ValueError(f"{name} must be contiguous")
+    kernel = (_lib.KERNEL_NORMALIZED if normalized else 0) | (_lib.KERNEL_DIAGONAL if anisotropic else 0)
     return _lib.InterpProblem(B, N, int(values.shape[2]), int(H), int(W), float(radius), int(tile),
-                              per_point)
+                              per_point, kernel)
 
 
 def aligned_buffer(nbytes: int, device) -> Tuple[torch.Tensor, int]:
@@ -88,9 +92,10 @@ class Workspace:
         self.buf, self.addr = aligned_buffer(self.nbytes, device)
 
 
-def forward(pos, sigma, values, H, W, radius=3.0, tile=DEFAULT_TILE):
+def forward(pos, sigma, values, H, W, radius=3.0, tile=DEFAULT_TILE, normalized=False,
+            anisotropic=False):
     """Runs interp_forward; returns (out, saved, workspace)."""
-    prob = problem(pos, sigma, values, H, W, radius, tile)
+    prob = problem(pos, sigma, values, H, W, radius, tile, normalized, anisotropic)
     dev = pos.device
     out = torch.empty((prob.B, prob.C, prob.H, prob.W), dtype=torch.float32, device=dev)
     saved = Saved(prob, dev)
@@ -102,11 +107,12 @@ def forward(pos, sigma, values, H, W, radius=3.0, tile=DEFAULT_TILE):
     return out, saved, work
 
 
-def forward_noalloc(pos, sigma, values, out, saved: Saved, H, W, radius=3.0, tile=DEFAULT_TILE):
+def forward_noalloc(pos, sigma, values, out, saved: Saved, H, W, radius=3.0, tile=DEFAULT_TILE,
+                    normalized=False, anisotropic=False):
     """Runs interp_forward_noalloc into the caller's out [B,C,H,W] and saved
     state: the library allocates nothing and uses its static per-GPU scratch
     as the workspace.  Returns out."""
-    prob = problem(pos, sigma, values, H, W, radius, tile)
+    prob = problem(pos, sigma, values, H, W, radius, tile, normalized, anisotropic)
     if (out.dtype != torch.float32 or not out.is_cuda or not out.is_contiguous()
             or tuple(out.shape) != (prob.B, prob.C, prob.H, prob.W)):
         raise ValueError("out must be a contiguous float32 [B, C, H, W] tensor on the device")
@@ -160,8 +166,8 @@ class InterpFunction(torch.autograd.Function):
     """Differentiable Gaussian-mixture interpolation (forward and backward in HIP)."""
 
     @staticmethod
-    def forward(ctx, pos, sigma, values, H, W, radius, tile):
-        out, saved, work = forward(pos, sigma, values, H, W, radius, tile)
+    def forward(ctx, pos, sigma, values, H, W, radius, tile, normalized=False, anisotropic=False):
+        out, saved, work = forward(pos, sigma, values, H, W, radius, tile, normalized, anisotropic)
         ctx.saved_state = saved
         ctx.work = work  # the backward reuses the forward's workspace
         ctx.save_for_backward(pos, sigma, values, out)
@@ -172,14 +178,20 @@ class InterpFunction(torch.autograd.Function):
         pos, sigma, values, out = ctx.saved_tensors
         need = ctx.needs_input_grad
         if not (need[0] or need[1] or need[2]):
-            return None, None, None, None, None, None, None
+            return (None,) * 9
         gp, gs, gv = backward(pos, sigma, values, out, ctx.saved_state, grad_out.float(),
                               need_pos=need[0], need_sigma=need[1], need_values=need[2],
                               work=ctx.work)
-        return gp, gs, gv, None, None, None, None
+        return (gp, gs, gv) + (None,) * 6
 
 
 def interpolate(pos: torch.Tensor, sigma: torch.Tensor, values: torch.Tensor, H: int, W: int,
-                radius: float = 3.0, tile: int = DEFAULT_TILE) -> torch.Tensor:
-    """Gaussian-mixture interpolation of scattered points onto an H x W grid (Eq. 1-2)."""
-    return InterpFunction.apply(pos, sigma, values, int(H), int(W), float(radius), int(tile))
+                radius: float = 3.0, tile: int = DEFAULT_TILE, normalized: bool = False,
+                anisotropic: bool = False) -> torch.Tensor:
+    """Gaussian-mixture interpolation of scattered points onto an H x W grid (Eq. 1-2).
+
+    normalized: keep the normal density's factor in each weight (Eq. 1 with
+    per-point sigmas); anisotropic: diagonal covariance, sigma = (sigma_x,
+    sigma_y) pairs [B, N, 2] or [B, 2]."""
+    return InterpFunction.apply(pos, sigma, values, int(H), int(W), float(radius), int(tile),
+                                bool(normalized), bool(anisotropic))

@@ -52,7 +52,8 @@ def test_sizes_valid_and_invalid(L):
     assert s >= 32 * 48 * 4 + (24 + 1) * 4 + 100 * (4 + 16 + 16)
     bad = [dict(C=0), dict(C=33), dict(radius=0.0), dict(radius=float("nan")), dict(radius=12.5),
            dict(tile=3), dict(tile=128), dict(H=0), dict(W=40000), dict(B=0), dict(N=-1),
-           dict(sigma_per_point=2), dict(B=2, N=1 << 30)]
+           dict(sigma_per_point=2), dict(B=2, N=1 << 30), dict(kernel=4), dict(kernel=-1),
+           dict(kernel=1, C=32)]
     for kw in bad:
         q = _prob(**kw)
         assert L.interp_workspace_bytes(ctypes.byref(q)) == 0, kw
