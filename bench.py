@@ -90,15 +90,16 @@ def bwd_ops_impl(C):
     return 11 + 2 * C
 
 
-def algorithmic_bytes(B, N, C, H, W, per_point, backward):
+def algorithmic_bytes(B, N, C, H, W, per_point, backward, vbytes=4):
     """HBM bytes the method must move: inputs read once, outputs written once
     (forward: points, image and Z; backward: G, out and Z read, points read,
-    gradients written)."""
-    pts = B * N * (8 + 4 * per_point + 4 * C)
-    fwd = pts + B * H * W * 4 * C + B * H * W * 4
+    gradients written).  vbytes: bytes per stored value (values, out, grad_out,
+    grad_values: 4 for float32, 2 for bfloat16 / half)."""
+    pts = B * N * (8 + 4 * per_point + vbytes * C)
+    fwd = pts + B * H * W * vbytes * C + B * H * W * 4
     if not backward:
         return fwd
-    bwd = B * H * W * (8 * C + 4) + pts + B * N * (4 * C + 8 + 4 * per_point)
+    bwd = B * H * W * (2 * vbytes * C + 4) + pts + B * N * (vbytes * C + 8 + 4 * per_point)
     return fwd + bwd
 
 
@@ -296,18 +297,24 @@ def measure_peaks(log):
     return peaks
 
 
-def measure_workload(wl, steps: int, warmup: int, backward: bool, log):
+def measure_workload(wl, steps: int, warmup: int, backward: bool, log, kernel: int = 0,
+                     storage: str = "float32"):
     """Times one named workload through the C ABI (eager calls, inputs in HBM):
     ms per step (forward, + backward when asked), Mpix/s, per-kernel event
     averages, the exact in-radius pair count, and the fraction of the ALU and
-    HBM ceilings the dominant kernels and the whole step reach."""
+    HBM ceilings the dominant kernels and the whole step reach.  kernel: the
+    INTERP_KERNEL_* flags (the pair count and ALU fractions are those of the
+    isotropic test, so a diagonal kernel reports times only); storage: the
+    dtype of values, out, grad_out and grad_values."""
     import ctypes
     import torch
     from paper_2012_13257_amd import _lib, interp
     pos, sig, val = _to_dev(wl)
-    prob = interp.problem(pos, sig, val, wl.H, wl.W, wl.radius)
+    val = val.to(getattr(torch, storage))
+    prob = interp.problem(pos, sig, val, wl.H, wl.W, wl.radius, normalized=bool(kernel & 1),
+                          anisotropic=bool(kernel & 2))
     L = _lib.lib()
-    out = torch.empty((wl.B, wl.C, wl.H, wl.W), device="cuda")
+    out = torch.empty((wl.B, wl.C, wl.H, wl.W), device="cuda", dtype=val.dtype)
     saved = interp.Saved(prob, pos.device)
     work = interp.Workspace(prob, pos.device)
     pb = ctypes.byref(prob)
@@ -315,7 +322,7 @@ def measure_workload(wl, steps: int, warmup: int, backward: bool, log):
     if backward:
         gen = torch.Generator(device="cuda")
         gen.manual_seed(wl.grad_seed)
-        G = torch.randn((wl.B, wl.C, wl.H, wl.W), generator=gen, device="cuda")
+        G = torch.randn((wl.B, wl.C, wl.H, wl.W), generator=gen, device="cuda").to(val.dtype)
         gp, gs, gv = torch.empty_like(pos), torch.empty_like(sig), torch.empty_like(val)
 
     def fwd():
@@ -336,12 +343,19 @@ def measure_workload(wl, steps: int, warmup: int, backward: bool, log):
     ms_step, _, _ = time_steps(step, steps, warmup, profile=False)
     ms_fwd, _, _ = time_steps(fwd, steps, warmup, profile=False)
     _, _, kernels = time_steps(step, steps, warmup, profile=True)
-    P = pair_count(wl.pos, wl.sigma, wl.H, wl.W, wl.radius)
     pix = wl.B * wl.H * wl.W
-    res = {"B": wl.B, "H": wl.H, "W": wl.W, "N": wl.N, "C": wl.C, "pairs_in_radius": P,
+    res = {"B": wl.B, "H": wl.H, "W": wl.W, "N": wl.N, "C": wl.C, "kernel": kernel,
+           "storage": storage,
            "ms_per_step": round(ms_step, 4), "mpix_s": round(pix / (ms_step * 1e-3) / 1e6, 1),
            "fwd_ms": round(ms_fwd, 4), "fwd_mpix_s": round(pix / (ms_fwd * 1e-3) / 1e6, 1),
            "kernels_us": {k: round(v["avg_us"], 2) for k, v in kernels.items()}}
+    if kernel & 2:
+        log(f"{wl.name} (kernel {kernel}): {res}")
+        del out, saved, work, G, gp, gs, gv, pos, sig, val
+        torch.cuda.empty_cache()
+        return res
+    P = pair_count(wl.pos, wl.sigma, wl.H, wl.W, wl.radius)
+    res["pairs_in_radius"] = P
     # ALU fraction of the two pair kernels (method count), HBM fraction of the
     # whole step (algorithmic bytes over the step time)
     for kname, ops in (("forward", fwd_ops(wl.C)), ("bwd_point", bwd_ops(wl.C))):
@@ -349,7 +363,8 @@ def measure_workload(wl, steps: int, warmup: int, backward: bool, log):
             a = P * ops / (kernels[kname]["avg_us"] * 1e-6) / 1e12
             res[kname + "_alu_frac"] = round(a / VALU_PEAK_TLANEOPS, 4)
     per_point = int(wl.sigma.ndim == 2)
-    nbytes = algorithmic_bytes(wl.B, wl.N, wl.C, wl.H, wl.W, per_point, backward)
+    nbytes = algorithmic_bytes(wl.B, wl.N, wl.C, wl.H, wl.W, per_point, backward,
+                               vbytes=val.element_size())
     res["algorithmic_bytes"] = nbytes
     res["step_hbm_frac"] = round(nbytes / (ms_step * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)
     # the step's own roofline: the larger of the ALU and HBM times at the peaks
@@ -701,6 +716,12 @@ def main():
             "cfg2_16x256x256_n65536_c3_fwd": measure_workload(synth.config2(), args.steps,
                                                               args.warmup, False, log),
             "cfg5_2x4096x4096_n4M_c16_fwd_bwd": measure_workload(synth.config5(), 5, 2, True, log),
+            "cfg5_2x4096x4096_n4M_c16_bf16_fwd_bwd": measure_workload(
+                synth.config5(), 5, 2, True, log, storage="bfloat16"),
+            "cfg3_normalised_fwd_bwd": measure_workload(synth.config3(), args.steps, args.warmup,
+                                                        True, log, kernel=1),
+            "cfg3_anisotropic_diagonal_fwd_bwd": measure_workload(
+                synth.config3_anisotropic(), args.steps, args.warmup, True, log, kernel=2),
             "optimise_1024x1024_n256k_pos_sigma": optimisation_step_timing(args.steps,
                                                                           args.warmup, log),
             "upsample_16x64x64_x4": upsampling_timing(args.steps, args.warmup, log),

@@ -72,6 +72,14 @@ enum {
  *       shared; grad_sigma has the same layout. */
 enum { INTERP_KERNEL_NORMALIZED = 1, INTERP_KERNEL_DIAGONAL = 2 };
 
+/* Storage type of the value-carrying arrays (interp_problem.storage):
+ * values, out, grad_out and grad_values (and the sorted value records kept
+ * from forward to backward) are float32, bfloat16 or IEEE half.  Every sum is
+ * taken in float32; out and grad_values are rounded to the storage type once,
+ * to nearest even.  Positions, sigmas, Z and their gradients stay float32.
+ * Non-float32 storage takes the default kernel (kernel = 0). */
+enum { INTERP_STORAGE_F32 = 0, INTERP_STORAGE_BF16 = 1, INTERP_STORAGE_F16 = 2 };
+
 /* Problem shape.
  *   B      images in the batch (>= 1)
  *   N      points per image (>= 0; N = 0 gives an all-zero output)
@@ -84,6 +92,7 @@ enum { INTERP_KERNEL_NORMALIZED = 1, INTERP_KERNEL_DIAGONAL = 2 };
  *          (with INTERP_KERNEL_DIAGONAL: [B, N, 2] and [B, 2])
  *   kernel 0 or INTERP_KERNEL_* flags (above); C is at most 31 with
  *          INTERP_KERNEL_NORMALIZED.  The serving path takes kernel 0 only.
+ *   storage INTERP_STORAGE_* (above); the serving path takes float32 only.
  */
 typedef struct interp_problem {
   int32_t B, N, C, H, W;
@@ -91,6 +100,7 @@ typedef struct interp_problem {
   int32_t tile;
   int32_t sigma_per_point;
   int32_t kernel;
+  int32_t storage;
 } interp_problem;
 
 /* Bytes of device scratch memory needed by interp_forward / interp_backward

@@ -23,6 +23,7 @@ INTERP_ENOTFOUND = -5
 
 NOALLOC_SCRATCH_BYTES = 64 << 20   # INTERP_NOALLOC_SCRATCH_BYTES
 KERNEL_NORMALIZED, KERNEL_DIAGONAL = 1, 2   # INTERP_KERNEL_* flags
+STORAGE_F32, STORAGE_BF16, STORAGE_F16 = 0, 1, 2   # INTERP_STORAGE_*
 
 QUEUED, RUNNING, DONE, FAILED = 0, 1, 2, 3
 
@@ -35,7 +36,7 @@ c_void_p = ctypes.c_void_p
 class InterpProblem(ctypes.Structure):
     _fields_ = [("B", c_int32), ("N", c_int32), ("C", c_int32), ("H", c_int32), ("W", c_int32),
                 ("radius", c_float), ("tile", c_int32), ("sigma_per_point", c_int32),
-                ("kernel", c_int32)]
+                ("kernel", c_int32), ("storage", c_int32)]
 
 
 class ServerConfig(ctypes.Structure):

@@ -8,6 +8,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <type_traits>
 
 #include "gmminterp.h"
 
@@ -83,6 +84,8 @@ struct Geometry {
   int per_point;
   int kern;                            // INTERP_KERNEL_* flags
   int nsig;                            // sigma values per point: 1 isotropic, 2 diagonal
+  int st;                              // INTERP_STORAGE_* of the value arrays
+  int vbytes;                          // bytes per stored value (4 or 2)
   int bx_blocks, by_blocks;            // 8x8 pixel blocks per image row / column
   int npass, dbits, kbits;             // radix sort of the bin keys
   int ntiles;                          // radix tiles per image
@@ -108,7 +111,7 @@ inline Layout make_layout(const Geometry& g) {
   L.offset = o; o = align_up(o + B * (size_t(g.nb) + 1) * 4);
   L.perm = o;   o = align_up(o + B * N * 4);
   L.geo = o;    o = align_up(o + B * N * 16);
-  L.col = o;    o = align_up(o + B * N * size_t(g.CS) * 4);
+  L.col = o;    o = align_up(o + B * N * size_t(g.CS) * g.vbytes);
   L.saved_bytes = o;
   o = 0;
   L.binof = o;  o = align_up(o + B * N * 4);
@@ -151,6 +154,10 @@ inline std::string make_geometry(const interp_problem* p, Geometry* g) {
     return "kernel must be a combination of INTERP_KERNEL_NORMALIZED and INTERP_KERNEL_DIAGONAL";
   const int norm = (p->kernel & INTERP_KERNEL_NORMALIZED) ? 1 : 0;
   if (p->C + norm > kMaxChannels) return "C must be at most 31 with a normalised kernel";
+  if (p->storage < INTERP_STORAGE_F32 || p->storage > INTERP_STORAGE_F16)
+    return "storage must be INTERP_STORAGE_F32, _BF16 or _F16";
+  if (p->storage != INTERP_STORAGE_F32 && p->kernel != 0)
+    return "bfloat16 and half storage take the default kernel";
   const int T = p->tile == 0 ? 8 : p->tile;
   if (T != 4 && T != 8 && T != 16 && T != 32 && T != 64) return "tile must be 0, 4, 8, 16, 32 or 64";
   const long long BN = (long long)p->B * p->N;
@@ -170,6 +177,8 @@ inline std::string make_geometry(const interp_problem* p, Geometry* g) {
   g->per_point = p->sigma_per_point;
   g->kern = p->kernel;
   g->nsig = (p->kernel & INTERP_KERNEL_DIAGONAL) ? 2 : 1;
+  g->st = p->storage;
+  g->vbytes = p->storage == INTERP_STORAGE_F32 ? 4 : 2;
   g->bx_blocks = (p->W + kBlockSide - 1) / kBlockSide;
   g->by_blocks = (p->H + kBlockSide - 1) / kBlockSide;
   radix_plan(g->nb, &g->npass, &g->dbits, &g->kbits);
@@ -186,6 +195,8 @@ inline std::string make_geometry(const interp_problem* p, Geometry* g) {
 struct ImageView {
   int N, C, H, W, T, nbx, nby, nb, CS, CP, per_point;
   int kern, nsig;           // kernel flags; sigma values per point (1 or 2)
+  int st;                   // INTERP_STORAGE_* of values, out, grad_out, grad_values, col
+  int values_vec4;          // C % 4 == 0 and values aligned to four elements: vector loads
   int zslot;                // normalised: record slot of the density factor, else -1
   float r2;                 // f32(radius * radius): the diagonal kernel's test
   int npass, dbits, kbits, ntiles, units256;
@@ -194,6 +205,8 @@ struct ImageView {
   // inputs / outputs
   const float2* pos;        // [N]
   const float* sigma;       // per point: [N, nsig]; shared: the image's nsig values
+  // values, out, grad_out, grad_values and col hold elements of the storage
+  // type (st); the kernels read and write them through Val<ST>
   const float* values;      // [N, C]
   float* out;               // [C, H, W]
   const float* grad_out;    // [C, H, W]
@@ -206,7 +219,7 @@ struct ImageView {
   int* offset;              // [nb + 1]
   int* perm;                // [N]
   float4* geo;              // [N]
-  float* col;               // [N, CS]
+  float* col;               // [N, CS] (storage type)
   // workspace
   int* binof;               // [N] bin key of each point (point order)
   int* keysF;               // [N] bin keys in sorted order
@@ -222,6 +235,12 @@ struct ImageView {
 
 template <typename T>
 __host__ __device__ inline T* shift(T* p, size_t n) { return p ? p + n : p; }
+// p advanced by n elements of ebytes bytes each
+template <typename T>
+__host__ __device__ inline T* bshift(T* p, size_t n, size_t ebytes) {
+  using Byte = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+  return p ? reinterpret_cast<T*>(reinterpret_cast<Byte*>(p) + n * ebytes) : p;
+}
 
 // The view of image b, given the view of image 0 of the same problem.
 __host__ __device__ inline ImageView image_of(const ImageView& v0, int b) {
@@ -230,18 +249,20 @@ __host__ __device__ inline ImageView image_of(const ImageView& v0, int b) {
   const size_t bb = b, N = v0.N, HW = size_t(v0.H) * v0.W;
   v.pos = shift(v0.pos, bb * N);
   v.sigma = shift(v0.sigma, (v0.per_point ? bb * N : bb) * v0.nsig);
-  v.values = shift(v0.values, bb * N * v0.C);
-  v.out = shift(v0.out, bb * v0.C * HW);
-  v.grad_out = shift(v0.grad_out, bb * v0.C * HW);
+  // value arrays step in elements of the storage type
+  const size_t vs = v0.st == INTERP_STORAGE_F32 ? 4 : 2;
+  v.values = bshift(v0.values, bb * N * v0.C, vs);
+  v.out = bshift(v0.out, bb * v0.C * HW, vs);
+  v.grad_out = bshift(v0.grad_out, bb * v0.C * HW, vs);
   v.grad_pos = shift(v0.grad_pos, bb * N * 2);
   v.grad_sigma = shift(v0.grad_sigma, (v0.per_point ? bb * N : bb) * v0.nsig);
-  v.grad_values = shift(v0.grad_values, bb * N * v0.C);
+  v.grad_values = bshift(v0.grad_values, bb * N * v0.C, vs);
   v.Z = shift(v0.Z, bb * HW);
   v.reach = shift(v0.reach, bb);
   v.offset = shift(v0.offset, bb * (size_t(v0.nb) + 1));
   v.perm = shift(v0.perm, bb * N);
   v.geo = shift(v0.geo, bb * N);
-  v.col = shift(v0.col, bb * N * v0.CS);
+  v.col = bshift(v0.col, bb * N * v0.CS, vs);
   v.binof = shift(v0.binof, bb * N);
   v.keysF = shift(v0.keysF, bb * N);
   v.kA = shift(v0.kA, bb * N);
@@ -270,7 +291,8 @@ inline ImageView make_view(const Geometry& g, const Layout& L, void* saved, void
   ImageView v;
   v.N = g.N; v.C = g.C; v.H = g.H; v.W = g.W; v.T = g.T; v.nbx = g.nbx; v.nby = g.nby; v.nb = g.nb;
   v.CS = g.CS; v.CP = g.CP; v.per_point = g.per_point;
-  v.kern = g.kern; v.nsig = g.nsig;
+  v.kern = g.kern; v.nsig = g.nsig; v.st = g.st;
+  v.values_vec4 = g.C % 4 == 0 && reinterpret_cast<uintptr_t>(values) % (4 * g.vbytes) == 0;
   v.zslot = (g.kern & INTERP_KERNEL_NORMALIZED) ? g.CT - 1 : -1;
   v.r2 = g.radius * g.radius;  // one rounded float multiply, as the test specifies
   v.npass = g.npass; v.dbits = g.dbits; v.kbits = g.kbits; v.ntiles = g.ntiles;

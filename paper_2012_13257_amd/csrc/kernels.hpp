@@ -108,6 +108,63 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// Storage of the value arrays (values, out, grad_out, grad_values and the
+// sorted value records): float32, bfloat16 or half.  Elements are widened
+// to float32 on load (exact) and rounded to nearest even on store.
+template <int ST> struct Val;
+template <> struct Val<INTERP_STORAGE_F32> {
+  __device__ static float load(const float* p, size_t i) { return p[i]; }
+  __device__ static void store(float* p, size_t i, float x) { p[i] = x; }
+  // elements 4g .. 4g+3
+  __device__ static float4 load4(const float* p, size_t g) {
+    return reinterpret_cast<const float4*>(p)[g];
+  }
+  __device__ static void store4(float* p, size_t g, float4 x) { reinterpret_cast<float4*>(p)[g] = x; }
+};
+__device__ inline float bf16_widen(unsigned h) { return __uint_as_float(h << 16); }
+__device__ inline unsigned bf16_round(float x) {
+  const unsigned u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;  // NaN stays NaN
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+template <> struct Val<INTERP_STORAGE_BF16> {
+  __device__ static float load(const float* p, size_t i) {
+    return bf16_widen(reinterpret_cast<const unsigned short*>(p)[i]);
+  }
+  __device__ static void store(float* p, size_t i, float x) {
+    reinterpret_cast<unsigned short*>(p)[i] = (unsigned short)bf16_round(x);
+  }
+  __device__ static float4 load4(const float* p, size_t g) {
+    const uint2 q = reinterpret_cast<const uint2*>(p)[g];
+    return make_float4(bf16_widen(q.x & 0xffffu), bf16_widen(q.x >> 16), bf16_widen(q.y & 0xffffu),
+                       bf16_widen(q.y >> 16));
+  }
+  __device__ static void store4(float* p, size_t g, float4 x) {
+    reinterpret_cast<uint2*>(p)[g] = make_uint2(bf16_round(x.x) | (bf16_round(x.y) << 16),
+                                                bf16_round(x.z) | (bf16_round(x.w) << 16));
+  }
+};
+template <> struct Val<INTERP_STORAGE_F16> {
+  __device__ static float load(const float* p, size_t i) {
+    return (float)reinterpret_cast<const _Float16*>(p)[i];
+  }
+  __device__ static void store(float* p, size_t i, float x) {
+    reinterpret_cast<_Float16*>(p)[i] = (_Float16)x;
+  }
+  __device__ static float4 load4(const float* p, size_t g) {
+    const uint2 q = reinterpret_cast<const uint2*>(p)[g];
+    _Float16 e[4];
+    __builtin_memcpy(e, &q, 8);
+    return make_float4((float)e[0], (float)e[1], (float)e[2], (float)e[3]);
+  }
+  __device__ static void store4(float* p, size_t g, float4 x) {
+    _Float16 e[4] = {(_Float16)x.x, (_Float16)x.y, (_Float16)x.z, (_Float16)x.w};
+    uint2 q;
+    __builtin_memcpy(&q, e, 8);
+    reinterpret_cast<uint2*>(p)[g] = q;
+  }
+};
+
 // ---------------------------------------------------------------------------
 // Binning: stable LSD radix sort of the bin keys (no global atomics)
 // ---------------------------------------------------------------------------
@@ -117,11 +174,17 @@ __device__ inline void wave_lds_sync() {
 __device__ inline float4 point_geo(const ImageView& v, int j) {
   return make_geo(v.pos[j], sigma2_of(v, j), v.radius, v.nsig == 2);
 }
+template <int ST = INTERP_STORAGE_F32>
 __device__ inline float4 point_values4(const ImageView& v, int j, int c) {
-  const float* src = v.values + (size_t)j * v.C;
+  const size_t base = (size_t)j * v.C;
   float q[4];
+  if (v.values_vec4 && c < v.C) {  // four values in one load
+    const float4 x = Val<ST>::load4(v.values, (base + c) / 4);
+    q[0] = x.x; q[1] = x.y; q[2] = x.z; q[3] = x.w;
+  } else {
 #pragma unroll
-  for (int i = 0; i < 4; ++i) q[i] = c + i < v.C ? src[c + i] : 0.0f;
+    for (int i = 0; i < 4; ++i) q[i] = c + i < v.C ? Val<ST>::load(v.values, base + c + i) : 0.0f;
+  }
   if (v.zslot >= c && v.zslot < c + 4) {
     const float z = density_factor(sigma2_of(v, j));
 #pragma unroll
@@ -135,6 +198,7 @@ __device__ inline float4 point_values4(const ImageView& v, int j, int c) {
 // tile's histogram of the lowest key digit.  lh: 256 ints of LDS.  With a
 // single bin (no radix pass) the point order is already sorted and the
 // sorted records are written here.
+template <int ST = INTERP_STORAGE_F32>
 __device__ inline void bin_keys(const ImageView& v, int tile, float* red4, int* lh) {
   const int t = threadIdx.x;
   const int width0 = v.npass > 0 ? min(v.dbits, v.kbits) : 0;
@@ -170,8 +234,8 @@ __device__ inline void bin_keys(const ImageView& v, int tile, float* red4, int* 
       v.keysF[j] = 0;
       v.perm[j] = j;
       v.geo[j] = make_geo(p[r], sg[r], v.radius, v.nsig == 2);
-      float4* dst = reinterpret_cast<float4*>(v.col + (size_t)j * v.CS);
-      for (int c = 0; c < v.CS; c += 4) dst[c / 4] = point_values4(v, j, c);
+      for (int c = 0; c < v.CS; c += 4)
+        Val<ST>::store4(v.col, (size_t)j * (v.CS / 4) + c / 4, point_values4<ST>(v, j, c));
     }
   }
   __syncthreads();
@@ -267,7 +331,7 @@ __host__ __device__ constexpr int radix_scatter_lds_ints() { return 6 * 256 + 4 
 // output.  The last pass writes the sorted keys, the permutation and the
 // sorted point records (x, y, k, R2 and the values padded to CS).
 // kWide: the records carry more than four values (CS > 4).
-template <bool kWide = false>
+template <bool kWide = false, int ST = INTERP_STORAGE_F32>
 __device__ inline void radix_scatter(const ImageView& v, int p, int tile, int* lds) {
   int* wrun = lds;                 // [4][256]
   int* base = lds + 1024;          // [256]
@@ -370,7 +434,7 @@ __device__ inline void radix_scatter(const ImageView& v, int p, int tile, int* l
     if constexpr (!kWide) {
       if (first) {
         eg[q] = point_geo(v, src);
-        ec[q] = point_values4(v, src, 0);
+        ec[q] = point_values4<ST>(v, src, 0);
       } else {
         eg[q] = (in_a ? geoA : geoB)[src];
         ec[q] = (in_a ? colA : colB)[src];
@@ -381,7 +445,7 @@ __device__ inline void radix_scatter(const ImageView& v, int p, int tile, int* l
 #pragma unroll
     for (int q = 0; q < kRadixItems; ++q) {
       eg[q] = point_geo(v, ej[q]);
-      ec[q] = point_values4(v, ej[q], 0);
+      ec[q] = point_values4<ST>(v, ej[q], 0);
     }
   }
   if (last) {
@@ -392,7 +456,7 @@ __device__ inline void radix_scatter(const ImageView& v, int p, int tile, int* l
         keysF[g] = ek[q];
         perm[g] = ej[q];
         geo[g] = eg[q];
-        reinterpret_cast<float4*>(col + (size_t)g * v.CS)[0] = ec[q];
+        Val<ST>::store4(col, (size_t)g * (v.CS / 4), ec[q]);
       }
     }
   } else {
@@ -418,11 +482,11 @@ __device__ inline void radix_scatter(const ImageView& v, int p, int tile, int* l
         float4 x[kExtra];
 #pragma unroll
         for (int r = 0; r < kExtra; ++r)
-          if (4 * (r + 1) < v.CS) x[r] = point_values4(v, ej[q], 4 * (r + 1));
-        float4* dst = reinterpret_cast<float4*>(col + (size_t)epos[q] * v.CS);
+          if (4 * (r + 1) < v.CS) x[r] = point_values4<ST>(v, ej[q], 4 * (r + 1));
+        const size_t g4 = (size_t)epos[q] * (v.CS / 4);
 #pragma unroll
         for (int r = 0; r < kExtra; ++r)
-          if (4 * (r + 1) < v.CS) dst[r + 1] = x[r];
+          if (4 * (r + 1) < v.CS) Val<ST>::store4(col, g4 + r + 1, x[r]);
       }
     }
   }
@@ -506,7 +570,7 @@ __host__ __device__ inline int fwd_tiles(int bx_blocks, int by_blocks) {
 // bin row), taken 64 at a time: each lane tests one candidate's disk against
 // the block, the hits are compacted in candidate order into the wavefront's
 // LDS list, and every lane then evaluates each hit for its pixel.
-template <int CT, int KV = 0>
+template <int CT, int KV = 0, int ST = INTERP_STORAGE_F32>
 __device__ inline void forward_tile(const ImageView& v, int tile, float4* s_geo /*[4][64]*/,
                                     float4* s_col /*[4][64*CS/4]*/) {
   constexpr int CS = CT < 4 ? 4 : CT;
@@ -560,9 +624,9 @@ __device__ inline void forward_tile(const ImageView& v, int tile, float4* s_geo 
         const int slot = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
                                                    __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0));
         lgeo[slot] = g;
-        const float4* cp = reinterpret_cast<const float4*>(cb + (size_t)jc * CS);
 #pragma unroll
-        for (int q = 0; q < CS / 4; ++q) lcol[slot * (CS / 4) + q] = cp[q];
+        for (int q = 0; q < CS / 4; ++q)
+          lcol[slot * (CS / 4) + q] = Val<ST>::load4(cb, (size_t)jc * (CS / 4) + q);
       }
       wave_lds_sync();
       const int nh = __popcll(mask);
@@ -589,7 +653,7 @@ __device__ inline void forward_tile(const ImageView& v, int tile, float4* s_geo 
     const size_t pix = (size_t)vv * v.W + u;
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
-      if (k < v.C) v.out[k * HW + pix] = Z > 0.0f ? acc[k] / Z : 0.0f;
+      if (k < v.C) Val<ST>::store(v.out, k * HW + pix, Z > 0.0f ? acc[k] / Z : 0.0f);
     }
     v.Z[pix] = Z;
   }
@@ -673,7 +737,7 @@ __device__ inline bool unit_is_heavy(const int cost[4]) {
 
 // mode 0: the whole unit, wavefront w on block w; mode 1 / 2: blocks 0-1 /
 // 2-3, wavefronts 2b and 2b+1 on the b-th of them.
-template <int CT, int KV = 0>
+template <int CT, int KV = 0, int ST = INTERP_STORAGE_F32>
 __device__ inline void forward_block_q(const ImageView& v, int unit, int mode, float4* s_rec) {
   static_assert(CT <= 4, "the quarter lists hold the values of a record in one float4");
   constexpr int NC = kNormalized<KV> ? CT - 1 : CT;  // channel slots (the last is the factor)
@@ -705,7 +769,7 @@ __device__ inline void forward_block_q(const ImageView& v, int unit, int mode, f
   const int by_lo = __builtin_amdgcn_readfirstlane(bb[2]);
   const int by_hi = active ? __builtin_amdgcn_readfirstlane(bb[3]) : by_lo - 1;
   const float4* gb = v.geo;
-  const float4* cb = reinterpret_cast<const float4*>(v.col);
+  const float* cb = v.col;  // one group of four stored values per record
 
   float Z[4], acc[4][CT];
 #pragma unroll
@@ -751,7 +815,7 @@ __device__ inline void forward_block_q(const ImageView& v, int unit, int mode, f
     float4 g_n = zero4, c_n = zero4;
     if (cur.r < nr && cur.c + lane < cur.rn) {
       g_n = gb[cur.rs + cur.c + lane];
-      c_n = cb[cur.rs + cur.c + lane];
+      c_n = Val<ST>::load4(cb, cur.rs + cur.c + lane);
     }
     while (cur.r < nr) {
       const bool in = cur.c + lane < cur.rn;
@@ -761,7 +825,7 @@ __device__ inline void forward_block_q(const ImageView& v, int unit, int mode, f
       if (split == 2) advance(nxt);
       if (nxt.r < nr && nxt.c + lane < nxt.rn) {
         g_n = gb[nxt.rs + nxt.c + lane];
-        c_n = cb[nxt.rs + nxt.c + lane];
+        c_n = Val<ST>::load4(cb, nxt.rs + nxt.c + lane);
       }
       cur = nxt;
       // disk of the candidate against the box of each quarter (conservative)
@@ -852,7 +916,7 @@ __device__ inline void forward_block_q(const ImageView& v, int unit, int mode, f
     const size_t pix = (size_t)vv * v.W + u;
 #pragma unroll
     for (int k = 0; k < CT; ++k) {
-      if (k < v.C) v.out[k * HW + pix] = Zo > 0.0f ? part[k] / Zo : 0.0f;
+      if (k < v.C) Val<ST>::store(v.out, k * HW + pix, Zo > 0.0f ? part[k] / Zo : 0.0f);
     }
     v.Z[pix] = Zo;
   }
@@ -864,7 +928,7 @@ __device__ inline void forward_block_q(const ImageView& v, int unit, int mode, f
 
 // unit = 256 pixels: G'_ik = G_ik / Z_i and beta_i = sum_k G_ik out_ik / Z_i,
 // packed per pixel as (G'_0 .. G'_{CT-1}, beta, zero padding)
-template <int CT>
+template <int CT, int ST = INTERP_STORAGE_F32>
 __device__ inline void bwd_pixel(const ImageView& v, int unit) {
   constexpr int CP = (CT + 1 + 3) / 4 * 4;
   const int HW = v.H * v.W;
@@ -881,9 +945,9 @@ __device__ inline void bwd_pixel(const ImageView& v, int unit) {
     for (int k = 0; k < CT; ++k) {
       if (k < v.C) {
         const size_t idx = (size_t)k * HW + i;
-        const float gk = v.grad_out[idx];
+        const float gk = Val<ST>::load(v.grad_out, idx);
         rec[k] = gk * a;
-        beta = __builtin_fmaf(gk, v.out[idx], beta);
+        beta = __builtin_fmaf(gk, Val<ST>::load(v.out, idx), beta);
       }
     }
     rec[CT] = beta * a;
@@ -916,7 +980,7 @@ constexpr int kBwdGroup = 4;
 // computes it, and the shared-sigma partial sum is taken in the original
 // point order: the output is deterministic.  lds: 256 + 32 ints; stage:
 // kBwdStageF4 float4s.
-template <int CT, int KV = 0>
+template <int CT, int KV = 0, int ST = INTERP_STORAGE_F32>
 __device__ inline void bwd_point(const ImageView& v, int unit, float* red4, int* lds,
                                  float4* stage) {
   constexpr int CS = CT < 4 ? 4 : CT;
@@ -985,7 +1049,7 @@ __device__ inline void bwd_point(const ImageView& v, int unit, float* red4, int*
     const float4 g = v.geo[t];
     float cc[CT];
 #pragma unroll
-    for (int k = 0; k < CT; ++k) cc[k] = v.col[(size_t)t * CS + k];
+    for (int k = 0; k < CT; ++k) cc[k] = Val<ST>::load(v.col, (size_t)t * CS + k);
     const float zeta = kN ? cc[CT - 1] : 1.0f;
     const int j = v.perm[t];
     const float2 sg = sigma2_of(v, j);
@@ -1132,7 +1196,7 @@ __device__ inline void bwd_point(const ImageView& v, int unit, float* red4, int*
     if (v.grad_values) {
 #pragma unroll
       for (int k = 0; k < NC; ++k)
-        if (k < v.C) v.grad_values[(size_t)j * v.C + k] = gc[k];
+        if (k < v.C) Val<ST>::store(v.grad_values, (size_t)j * v.C + k, gc[k]);
     }
   }
   if (!v.per_point && v.grad_sigma) {

@@ -383,6 +383,7 @@ int interp_submit(interp_server* s, const interp_request* req, uint64_t* ticket)
   if (rq.g.B != 1) return fail(INTERP_EINVAL, "a serving request has B = 1");
   if (rq.g.C > serve::kServeMaxC) return fail(INTERP_EINVAL, "the serving path takes C <= 4");
   if (rq.g.kern != 0) return fail(INTERP_EINVAL, "the serving path takes the default kernel only");
+  if (rq.g.st != INTERP_STORAGE_F32) return fail(INTERP_EINVAL, "the serving path takes float32 storage only");
   if (rq.g.npass > serve::kServePasses) return fail(INTERP_EINVAL, "too many bins for the serving path");
   if (rq.g.N > 0 && (!req->pos || !req->sigma || !req->values))
     return fail(INTERP_EINVAL, "pos, sigma and values must not be NULL when N > 0");

@@ -16,12 +16,13 @@ namespace {
 // faster, the key pass ~10%).
 __device__ inline int xcd_tile(int per8) { return (blockIdx.x & 7) * per8 + (blockIdx.x >> 3); }
 
+template <int ST>
 __global__ __launch_bounds__(256) void k_bin_keys(ImageView v0, int per8) {
   __shared__ float red4[4];
   __shared__ int lh[256];
   const int tile = xcd_tile(per8);
   if (tile >= v0.ntiles) return;
-  dev::bin_keys(image_of(v0, blockIdx.y), tile, red4, lh);
+  dev::bin_keys<ST>(image_of(v0, blockIdx.y), tile, red4, lh);
 }
 
 __global__ __launch_bounds__(256) void k_radix_hist(ImageView v0, int p, int per8) {
@@ -36,12 +37,12 @@ __global__ __launch_bounds__(256) void k_radix_scan(ImageView v0, int p) {
   dev::radix_scan_digit(image_of(v0, blockIdx.y), p, blockIdx.x, tmp4);
 }
 
-template <bool kWide>
+template <bool kWide, int ST>
 __global__ __launch_bounds__(256) void k_radix_scatter(ImageView v0, int p, int per8) {
   __shared__ int lds[dev::radix_scatter_lds_ints()];
   const int tile = xcd_tile(per8);
   if (tile >= v0.ntiles) return;
-  dev::radix_scatter<kWide>(image_of(v0, blockIdx.y), p, tile, lds);
+  dev::radix_scatter<kWide, ST>(image_of(v0, blockIdx.y), p, tile, lds);
 }
 
 // also clears the counters of the forward's work order (fplan, 64 ints)
@@ -108,7 +109,7 @@ __global__ __launch_bounds__(256) void k_fwd_plan(ImageView v0, int units, int t
 // fills in the light ones as compute units free up (a unit's result does not
 // depend on which workgroup computes it or when).  More channels: one
 // workgroup per 16x16 tile, a wavefront per 8x8 block.
-template <int CT, int KV>
+template <int CT, int KV, int ST>
 __global__ __launch_bounds__(256) void k_forward_lpt(ImageView v0, int units, int total,
                                                      const int* fplan) {
   __shared__ float4 s_rec[dev::fwd_quarter_lds_f4()];
@@ -130,35 +131,35 @@ __global__ __launch_bounds__(256) void k_forward_lpt(ImageView v0, int units, in
   const int item = fplan[64 + (size_t)(kPlanBuckets - 1 - k) * 2 * total + (w - before)];
   const int id = item >> 2;
   const int b = id / units;
-  dev::forward_block_q<CT, KV>(image_of(v0, b), id - b * units, item & 3, s_rec);
+  dev::forward_block_q<CT, KV, ST>(image_of(v0, b), id - b * units, item & 3, s_rec);
 }
 
-template <int CT, int KV>
+template <int CT, int KV, int ST>
 __global__ __launch_bounds__(256) void k_forward(ImageView v0, int tiles_per_image) {
   __shared__ float4 s_geo[4 * 64];
   __shared__ float4 s_col[4 * 64 * (CT / 4)];
   const int t = blockIdx.x;
   const int b = t / tiles_per_image;
-  dev::forward_tile<CT, KV>(image_of(v0, b), t - b * tiles_per_image, s_geo, s_col);
+  dev::forward_tile<CT, KV, ST>(image_of(v0, b), t - b * tiles_per_image, s_geo, s_col);
 }
 
-template <int CT>
+template <int CT, int ST>
 __global__ __launch_bounds__(256) void k_bwd_pixel(ImageView v0) {
-  dev::bwd_pixel<CT>(image_of(v0, blockIdx.y), blockIdx.x);
+  dev::bwd_pixel<CT, ST>(image_of(v0, blockIdx.y), blockIdx.x);
 }
 
 // The dispatcher hands workgroup i to XCD i % 8; units of 256 sorted points
 // are assigned so that each XCD walks one contiguous eighth of the sorted
 // order -- a band of the image whose pixel records stay in that XCD's L2 --
 // instead of every XCD touching the whole image.  per8 = ceil(units / 8).
-template <int CT, int KV>
+template <int CT, int KV, int ST>
 __global__ __launch_bounds__(256) void k_bwd_point(ImageView v0, int per8) {
   __shared__ float red4[4];
   __shared__ int lds[256 + 64];
   __shared__ float4 stage[dev::kBwdStageF4];
   const int unit = (blockIdx.x & 7) * per8 + (blockIdx.x >> 3);
   if ((int)(blockIdx.x >> 3) >= per8 || unit >= v0.units256) return;
-  dev::bwd_point<CT, KV>(image_of(v0, blockIdx.y), unit, red4, lds, stage);
+  dev::bwd_point<CT, KV, ST>(image_of(v0, blockIdx.y), unit, red4, lds, stage);
 }
 
 __global__ __launch_bounds__(256) void k_bwd_sigma_sum(ImageView v0) {
@@ -174,7 +175,7 @@ __global__ __launch_bounds__(256) void k_debug_count(ImageView v0, int* count) {
 
 inline unsigned cdiv(long long n, int d) { return (unsigned)((n + d - 1) / d); }
 
-template <int CT, int KV>
+template <int CT, int KV, int ST>
 hipError_t launch_forward_t(const Geometry& g, const ImageView& v0, int* fplan, hipStream_t st) {
   if constexpr (CT <= 4) {
     const int total = g.fwd_units * g.B;  // checked against 2^31 / kPlanBuckets
@@ -184,29 +185,29 @@ hipError_t launch_forward_t(const Geometry& g, const ImageView& v0, int* fplan, 
                          total, fplan);
     }
     ProfRange pr_("forward", st);
-    hipLaunchKernelGGL((k_forward_lpt<CT, KV>), dim3((unsigned)(2 * total)), dim3(256), 0, st, v0,
+    hipLaunchKernelGGL((k_forward_lpt<CT, KV, ST>), dim3((unsigned)(2 * total)), dim3(256), 0, st, v0,
                        g.fwd_units, total, fplan);
   } else {
     const int per = dev::fwd_tiles(g.bx_blocks, g.by_blocks);
     const long long total = (long long)per * g.B;
     if (total >= (1LL << 31)) return hipErrorInvalidValue;
     ProfRange pr_("forward", st);
-    hipLaunchKernelGGL((k_forward<CT, KV>), dim3((unsigned)total), dim3(256), 0, st, v0, per);
+    hipLaunchKernelGGL((k_forward<CT, KV, ST>), dim3((unsigned)total), dim3(256), 0, st, v0, per);
   }
   return hipSuccess;
 }
 
-template <int CT, int KV>
+template <int CT, int KV, int ST>
 hipError_t launch_backward_t(const Geometry& g, const ImageView& v0, hipStream_t st) {
   {
     ProfRange pr_("bwd_pixel", st);
-    hipLaunchKernelGGL(k_bwd_pixel<CT>, dim3(cdiv((long long)g.H * g.W, 256), g.B), dim3(256), 0,
+    hipLaunchKernelGGL((k_bwd_pixel<CT, ST>), dim3(cdiv((long long)g.H * g.W, 256), g.B), dim3(256), 0,
                        st, v0);
   }
   if (g.N > 0) {
     ProfRange pr_("bwd_point", st);
     const int per8 = (g.units256 + 7) / 8;
-    hipLaunchKernelGGL((k_bwd_point<CT, KV>), dim3(8 * per8, g.B), dim3(256), 0, st, v0, per8);
+    hipLaunchKernelGGL((k_bwd_point<CT, KV, ST>), dim3(8 * per8, g.B), dim3(256), 0, st, v0, per8);
   }
   if (!g.per_point && v0.grad_sigma) {
     ProfRange pr_("bwd_sigma_sum", st);
@@ -217,43 +218,43 @@ hipError_t launch_backward_t(const Geometry& g, const ImageView& v0, hipStream_t
 
 // Channel-count dispatch of one kernel variant (a normalised kernel's
 // records hold the density factor in an extra slot, so its CT is at least 2).
-template <int KV>
+template <int KV, int ST>
 hipError_t launch_forward_kv(const Geometry& g, const ImageView& v0, int* fplan, hipStream_t st) {
   constexpr bool kN = (KV & INTERP_KERNEL_NORMALIZED) != 0;
   switch (g.CT) {
-    case 1: if constexpr (!kN) return launch_forward_t<1, KV>(g, v0, fplan, st); break;
-    case 2: return launch_forward_t<2, KV>(g, v0, fplan, st);
-    case 3: return launch_forward_t<3, KV>(g, v0, fplan, st);
-    case 4: return launch_forward_t<4, KV>(g, v0, fplan, st);
-    case 8: return launch_forward_t<8, KV>(g, v0, fplan, st);
-    case 16: return launch_forward_t<16, KV>(g, v0, fplan, st);
-    case 32: return launch_forward_t<32, KV>(g, v0, fplan, st);
+    case 1: if constexpr (!kN) return launch_forward_t<1, KV, ST>(g, v0, fplan, st); break;
+    case 2: return launch_forward_t<2, KV, ST>(g, v0, fplan, st);
+    case 3: return launch_forward_t<3, KV, ST>(g, v0, fplan, st);
+    case 4: return launch_forward_t<4, KV, ST>(g, v0, fplan, st);
+    case 8: return launch_forward_t<8, KV, ST>(g, v0, fplan, st);
+    case 16: return launch_forward_t<16, KV, ST>(g, v0, fplan, st);
+    case 32: return launch_forward_t<32, KV, ST>(g, v0, fplan, st);
   }
   return hipErrorInvalidValue;
 }
 
-template <int KV>
+template <int KV, int ST>
 hipError_t launch_backward_kv(const Geometry& g, const ImageView& v0, hipStream_t st) {
   constexpr bool kN = (KV & INTERP_KERNEL_NORMALIZED) != 0;
   switch (g.CT) {
-    case 1: if constexpr (!kN) return launch_backward_t<1, KV>(g, v0, st); break;
-    case 2: return launch_backward_t<2, KV>(g, v0, st);
-    case 3: return launch_backward_t<3, KV>(g, v0, st);
-    case 4: return launch_backward_t<4, KV>(g, v0, st);
-    case 8: return launch_backward_t<8, KV>(g, v0, st);
-    case 16: return launch_backward_t<16, KV>(g, v0, st);
-    case 32: return launch_backward_t<32, KV>(g, v0, st);
+    case 1: if constexpr (!kN) return launch_backward_t<1, KV, ST>(g, v0, st); break;
+    case 2: return launch_backward_t<2, KV, ST>(g, v0, st);
+    case 3: return launch_backward_t<3, KV, ST>(g, v0, st);
+    case 4: return launch_backward_t<4, KV, ST>(g, v0, st);
+    case 8: return launch_backward_t<8, KV, ST>(g, v0, st);
+    case 16: return launch_backward_t<16, KV, ST>(g, v0, st);
+    case 32: return launch_backward_t<32, KV, ST>(g, v0, st);
   }
   return hipErrorInvalidValue;
 }
 
-}  // namespace
-
-hipError_t launch_forward_all(const Geometry& g, const ImageView& v0, int* fplan, hipStream_t st) {
+// Binning (a1-a5) for values stored as ST.
+template <int ST>
+hipError_t launch_binning(const Geometry& g, const ImageView& v0, int* fplan, hipStream_t st) {
   const int per8 = (g.ntiles + 7) / 8;  // radix tiles per XCD
   if (g.N > 0) {
     ProfRange pr_("bin_keys", st);
-    hipLaunchKernelGGL(k_bin_keys, dim3(8 * per8, g.B), dim3(256), 0, st, v0, per8);
+    hipLaunchKernelGGL((k_bin_keys<ST>), dim3(8 * per8, g.B), dim3(256), 0, st, v0, per8);
   }
   for (int p = 0; p < g.npass && g.N > 0; ++p) {
     if (p > 0) {
@@ -268,11 +269,11 @@ hipError_t launch_forward_all(const Geometry& g, const ImageView& v0, int* fplan
     {
       ProfRange pr_("radix_scatter", st);
       if (g.CS > 4)
-        hipLaunchKernelGGL(k_radix_scatter<true>, dim3(8 * per8, g.B), dim3(256), 0, st, v0, p,
-                           per8);
+        hipLaunchKernelGGL((k_radix_scatter<true, ST>), dim3(8 * per8, g.B), dim3(256), 0, st, v0,
+                           p, per8);
       else
-        hipLaunchKernelGGL(k_radix_scatter<false>, dim3(8 * per8, g.B), dim3(256), 0, st, v0, p,
-                           per8);
+        hipLaunchKernelGGL((k_radix_scatter<false, ST>), dim3(8 * per8, g.B), dim3(256), 0, st,
+                           v0, p, per8);
     }
   }
   {
@@ -280,14 +281,33 @@ hipError_t launch_forward_all(const Geometry& g, const ImageView& v0, int* fplan
     hipLaunchKernelGGL(k_bin_finish, dim3(dev::finish_units(g.N), g.B), dim3(256), 0, st, v0,
                        fplan);
   }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  switch (g.kern) {
-    case 0: e = launch_forward_kv<0>(g, v0, fplan, st); break;
-    case 1: e = launch_forward_kv<1>(g, v0, fplan, st); break;
-    case 2: e = launch_forward_kv<2>(g, v0, fplan, st); break;
-    case 3: e = launch_forward_kv<3>(g, v0, fplan, st); break;
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// Kernel variants take float32 storage; the default kernel any storage.
+hipError_t launch_forward_all(const Geometry& g, const ImageView& v0, int* fplan, hipStream_t st) {
+  hipError_t e;
+  switch (g.st) {
+    case INTERP_STORAGE_F32: e = launch_binning<INTERP_STORAGE_F32>(g, v0, fplan, st); break;
+    case INTERP_STORAGE_BF16: e = launch_binning<INTERP_STORAGE_BF16>(g, v0, fplan, st); break;
+    case INTERP_STORAGE_F16: e = launch_binning<INTERP_STORAGE_F16>(g, v0, fplan, st); break;
     default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  if (g.st == INTERP_STORAGE_BF16) {
+    e = launch_forward_kv<0, INTERP_STORAGE_BF16>(g, v0, fplan, st);
+  } else if (g.st == INTERP_STORAGE_F16) {
+    e = launch_forward_kv<0, INTERP_STORAGE_F16>(g, v0, fplan, st);
+  } else {
+    switch (g.kern) {
+      case 0: e = launch_forward_kv<0, 0>(g, v0, fplan, st); break;
+      case 1: e = launch_forward_kv<1, 0>(g, v0, fplan, st); break;
+      case 2: e = launch_forward_kv<2, 0>(g, v0, fplan, st); break;
+      case 3: e = launch_forward_kv<3, 0>(g, v0, fplan, st); break;
+      default: return hipErrorInvalidValue;
+    }
   }
   if (e != hipSuccess) return e;
   return hipGetLastError();
@@ -295,12 +315,18 @@ hipError_t launch_forward_all(const Geometry& g, const ImageView& v0, int* fplan
 
 hipError_t launch_backward_all(const Geometry& g, const ImageView& v0, hipStream_t st) {
   hipError_t e;
-  switch (g.kern) {
-    case 0: e = launch_backward_kv<0>(g, v0, st); break;
-    case 1: e = launch_backward_kv<1>(g, v0, st); break;
-    case 2: e = launch_backward_kv<2>(g, v0, st); break;
-    case 3: e = launch_backward_kv<3>(g, v0, st); break;
-    default: return hipErrorInvalidValue;
+  if (g.st == INTERP_STORAGE_BF16) {
+    e = launch_backward_kv<0, INTERP_STORAGE_BF16>(g, v0, st);
+  } else if (g.st == INTERP_STORAGE_F16) {
+    e = launch_backward_kv<0, INTERP_STORAGE_F16>(g, v0, st);
+  } else {
+    switch (g.kern) {
+      case 0: e = launch_backward_kv<0, 0>(g, v0, st); break;
+      case 1: e = launch_backward_kv<1, 0>(g, v0, st); break;
+      case 2: e = launch_backward_kv<2, 0>(g, v0, st); break;
+      case 3: e = launch_backward_kv<3, 0>(g, v0, st); break;
+      default: return hipErrorInvalidValue;
+    }
   }
   if (e != hipSuccess) return e;
   return hipGetLastError();

@@ -23,13 +23,19 @@ __all__ = ["interpolate", "InterpFunction", "forward", "forward_noalloc", "backw
 
 DEFAULT_TILE = 8
 
+# storage type of values, out, grad_out and grad_values, from values' dtype
+_STORAGE = {torch.float32: _lib.STORAGE_F32, torch.bfloat16: _lib.STORAGE_BF16,
+            torch.float16: _lib.STORAGE_F16}
+
 
 def problem(pos: torch.Tensor, sigma: torch.Tensor, values: torch.Tensor, H: int, W: int,
             radius: float = 3.0, tile: int = DEFAULT_TILE, normalized: bool = False,
             anisotropic: bool = False) -> _lib.InterpProblem:
     """The C-ABI problem descriptor of these tensors.  normalized keeps the
     density factor in each weight; anisotropic takes a diagonal covariance,
-    sigma then holding (sigma_x, sigma_y) pairs: [B, N, 2] or [B, 2]."""
+    sigma then holding (sigma_x, sigma_y) pairs: [B, N, 2] or [B, 2].  The
+    dtype of values (float32, bfloat16 or float16) is the storage type of
+    values, out, grad_out and grad_values; sums are float32 throughout."""
     if pos.dim() != 3 or pos.shape[2] != 2:
         raise ValueError("pos must be [B, N, 2]")
     B, N = int(pos.shape[0]), int(pos.shape[1])
@@ -45,15 +51,17 @@ def problem(pos: torch.Tensor, sigma: torch.Tensor, values: torch.Tensor, H: int
         raise ValueError("sigma must be [B, N] or [B]" if k == 1 else
                          "anisotropic sigma must be [B, N, 2] or [B, 2]")
     for name, t in (("pos", pos), ("sigma", sigma), ("values", values)):
-        if t.dtype != torch.float32:
+        if name != "values" and t.dtype != torch.float32:
             raise ValueError(f"{name} must be float32")
         if not t.is_cuda:
             raise ValueError(f"{name} must be on the ROCm device")
         if not t.is_contiguous():
             raise ValueError(f"{name} must be contiguous")
+    if values.dtype not in _STORAGE:
+        raise ValueError("values must be float32, bfloat16 or float16")
     kernel = (_lib.KERNEL_NORMALIZED if normalized else 0) | (_lib.KERNEL_DIAGONAL if anisotropic else 0)
     return _lib.InterpProblem(B, N, int(values.shape[2]), int(H), int(W), float(radius), int(tile),
-                              per_point, kernel)
+                              per_point, kernel, _STORAGE[values.dtype])
 
 
 def aligned_buffer(nbytes: int, device) -> Tuple[torch.Tensor, int]:
@@ -97,7 +105,7 @@ def forward(pos, sigma, values, H, W, radius=3.0, tile=DEFAULT_TILE, normalized=
     """Runs interp_forward; returns (out, saved, workspace)."""
     prob = problem(pos, sigma, values, H, W, radius, tile, normalized, anisotropic)
     dev = pos.device
-    out = torch.empty((prob.B, prob.C, prob.H, prob.W), dtype=torch.float32, device=dev)
+    out = torch.empty((prob.B, prob.C, prob.H, prob.W), dtype=values.dtype, device=dev)
     saved = Saved(prob, dev)
     work = Workspace(prob, dev)
     rc = _lib.lib().interp_forward(ctypes.byref(prob), _ptr(pos), _ptr(sigma), _ptr(values),
@@ -113,9 +121,9 @@ def forward_noalloc(pos, sigma, values, out, saved: Saved, H, W, radius=3.0, til
     state: the library allocates nothing and uses its static per-GPU scratch
     as the workspace.  Returns out."""
     prob = problem(pos, sigma, values, H, W, radius, tile, normalized, anisotropic)
-    if (out.dtype != torch.float32 or not out.is_cuda or not out.is_contiguous()
+    if (out.dtype != values.dtype or not out.is_cuda or not out.is_contiguous()
             or tuple(out.shape) != (prob.B, prob.C, prob.H, prob.W)):
-        raise ValueError("out must be a contiguous float32 [B, C, H, W] tensor on the device")
+        raise ValueError("out must be a contiguous [B, C, H, W] tensor of values' dtype on the device")
     rc = _lib.lib().interp_forward_noalloc(ctypes.byref(prob), _ptr(pos), _ptr(sigma),
                                            _ptr(values), _ptr(out), saved.addr, saved.nbytes,
                                            _stream(pos.device))
@@ -128,8 +136,8 @@ def backward(pos, sigma, values, out, saved: Saved, grad_out, need_pos=True, nee
     """Runs interp_backward; returns (grad_pos, grad_sigma, grad_values) (None where not needed)."""
     prob = saved.prob
     dev = pos.device
-    if grad_out.dtype != torch.float32 or not grad_out.is_cuda:
-        raise ValueError("grad_out must be float32 on the ROCm device")
+    if grad_out.dtype != values.dtype or not grad_out.is_cuda:
+        raise ValueError("grad_out must have the dtype of values and be on the ROCm device")
     grad_out = grad_out.contiguous()
     if tuple(grad_out.shape) != (prob.B, prob.C, prob.H, prob.W):
         raise ValueError("grad_out must be [B, C, H, W]")
@@ -179,7 +187,7 @@ class InterpFunction(torch.autograd.Function):
         need = ctx.needs_input_grad
         if not (need[0] or need[1] or need[2]):
             return (None,) * 9
-        gp, gs, gv = backward(pos, sigma, values, out, ctx.saved_state, grad_out.float(),
+        gp, gs, gv = backward(pos, sigma, values, out, ctx.saved_state, grad_out.to(values.dtype),
                               need_pos=need[0], need_sigma=need[1], need_values=need[2],
                               work=ctx.work)
         return (gp, gs, gv) + (None,) * 6

@@ -32,7 +32,7 @@ import numpy as np
 
 __all__ = [
     "Workload", "uniform_points", "blob_points", "random_workload",
-    "config1", "config2", "config3", "config4_trace", "config5",
+    "config1", "config2", "config3", "config3_anisotropic", "config4_trace", "config5",
     "ServingRequest", "CONFIGS", "natural_image", "sample_image_points",
 ]
 
@@ -207,6 +207,16 @@ def config3(seed: int = 1003) -> Workload:
     val = rng.random((1, N, 3), dtype=np.float32)
     sig = _log_uniform(rng, (1, N), 0.5, 2.0)
     return Workload("cfg3_1024x1024_n1M_c3", pos, sig, val, H, W, 3.0, grad_seed=seed + 7919)
+
+
+def config3_anisotropic(seed: int = 1003) -> Workload:
+    """The 1024x1024, N=2**20 workload with a diagonal covariance per point:
+    (sigma_x, sigma_y) drawn independently log-uniform in [0.5, 2]."""
+    wl = config3(seed)
+    rng = np.random.default_rng(seed + 17)
+    sig = _log_uniform(rng, (1, wl.N, 2), 0.5, 2.0)
+    return Workload("cfg3_aniso_1024x1024_n1M_c3", wl.pos, sig, wl.values, wl.H, wl.W, 3.0,
+                    grad_seed=wl.grad_seed)
 
 
 def config5(seed: int = 1005, B: int = 2, size: int = 4096, N: int = 1 << 22) -> Workload:
