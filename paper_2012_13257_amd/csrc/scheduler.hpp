@@ -271,8 +271,13 @@ class Scheduler {
       if (outstanding_ == 0) done_cv_.notify_all();
       if (stop_) break;
       if (busy) {
-        // a batch is on the device: poll again shortly, waking up early for arrivals
-        cv_.wait_for(lk, std::chrono::microseconds(5));
+        // a batch is on the device: poll its completion again at once (a
+        // timed wait would sleep for the timer's slack, tens of microseconds,
+        // which small requests would see as latency); the lock is dropped
+        // so that submit and poll get in between rounds
+        lk.unlock();
+        std::this_thread::yield();
+        lk.lock();
       } else {
         cv_.wait_for(lk, std::chrono::milliseconds(2),
                      [this] { return stop_ || !queue_.empty() || !pending_.empty(); });

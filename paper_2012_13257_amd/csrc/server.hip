@@ -150,37 +150,47 @@ __global__ __launch_bounds__(256) void kj_phase(const JobTable* __restrict__ T) 
   }
 }
 
+// Grid sizes of the job-table kernels.  A full grid holds as many
+// workgroups as fit the chip at once; a batch whose every phase has at most
+// kSmallUnits units replays graphs of kSmallGrid-workgroup kernels instead,
+// which the dispatcher starts and drains far sooner (a small request then
+// does not pay for thousands of workgroups with no work, per phase).  A
+// unit's result does not depend on the grid that computes it.
+constexpr int kSmallGrid = 64;
+constexpr int kSmallUnits = 2 * kSmallGrid;
+
 // cus: compute units of the device; the grid is a multiple of 8 (the
 // radix phases deal their tiles to the eight XCDs)
 template <int PH>
-void enqueue_phase(const JobTable* dtab, hipStream_t st, int cus) {
-  const int grid = (phase_wgs_per_cu<PH>() * cus + 7) / 8 * 8;
+void enqueue_phase(const JobTable* dtab, hipStream_t st, int cus, bool small) {
+  const int full = (phase_wgs_per_cu<PH>() * cus + 7) / 8 * 8;
+  const int grid = small ? std::min(full, kSmallGrid) : full;
   hipLaunchKernelGGL(kj_phase<PH>, dim3(grid), dim3(256), 0, st, dtab);
 }
 
 // The phase sequence of a batch whose jobs need at most np radix passes
 // (1..3; a job with none is covered too) and, if bwd, a backward.  The first
 // pass's histogram comes from the key phase, so there is no PH_HIST0.
-void enqueue_phases(const JobTable* dtab, hipStream_t st, int cus, int np, bool bwd) {
-  enqueue_phase<PH_KEYS>(dtab, st, cus);
-  enqueue_phase<PH_SCAN0>(dtab, st, cus);
-  enqueue_phase<PH_SCAT0>(dtab, st, cus);
+void enqueue_phases(const JobTable* dtab, hipStream_t st, int cus, int np, bool bwd, bool small) {
+  enqueue_phase<PH_KEYS>(dtab, st, cus, small);
+  enqueue_phase<PH_SCAN0>(dtab, st, cus, small);
+  enqueue_phase<PH_SCAT0>(dtab, st, cus, small);
   if (np >= 2) {
-    enqueue_phase<PH_HIST1>(dtab, st, cus);
-    enqueue_phase<PH_SCAN1>(dtab, st, cus);
-    enqueue_phase<PH_SCAT1>(dtab, st, cus);
+    enqueue_phase<PH_HIST1>(dtab, st, cus, small);
+    enqueue_phase<PH_SCAN1>(dtab, st, cus, small);
+    enqueue_phase<PH_SCAT1>(dtab, st, cus, small);
   }
   if (np >= 3) {
-    enqueue_phase<PH_HIST2>(dtab, st, cus);
-    enqueue_phase<PH_SCAN2>(dtab, st, cus);
-    enqueue_phase<PH_SCAT2>(dtab, st, cus);
+    enqueue_phase<PH_HIST2>(dtab, st, cus, small);
+    enqueue_phase<PH_SCAN2>(dtab, st, cus, small);
+    enqueue_phase<PH_SCAT2>(dtab, st, cus, small);
   }
-  enqueue_phase<PH_FINISH>(dtab, st, cus);
-  enqueue_phase<PH_FWD>(dtab, st, cus);
+  enqueue_phase<PH_FINISH>(dtab, st, cus, small);
+  enqueue_phase<PH_FWD>(dtab, st, cus, small);
   if (bwd) {
-    enqueue_phase<PH_BPIX>(dtab, st, cus);
-    enqueue_phase<PH_BPOINT>(dtab, st, cus);
-    enqueue_phase<PH_BSIG>(dtab, st, cus);
+    enqueue_phase<PH_BPIX>(dtab, st, cus, small);
+    enqueue_phase<PH_BPOINT>(dtab, st, cus, small);
+    enqueue_phase<PH_BSIG>(dtab, st, cus, small);
   }
 }
 
@@ -209,6 +219,10 @@ class GpuExecutor {
     if (budget) {
       e = hipMalloc(&arena_, budget);
       if (e != hipSuccess) return fail_hip(e, "hipMalloc(arena)");
+      // touch every page of the arena once now: the first use of fresh device
+      // memory is slow, and no request should pay for it
+      e = hipMemset(arena_, 0, budget);
+      if (e != hipSuccess) return fail_hip(e, "hipMemset(arena)");
     }
     for (int c = 0; c < kContexts; ++c) {
       Ctx& x = ctx_[c];
@@ -222,18 +236,20 @@ class GpuExecutor {
       // an empty table so that the capture below reads defined memory
       if ((e = hipMemcpy(x.dtab, x.htab, sizeof(JobTable), hipMemcpyHostToDevice)) != hipSuccess)
         return fail_hip(e, "hipMemcpy(table)");
-      // one graph per (radix passes, backward) combination, captured once;
-      // a batch replays the one that covers the most passes and the backward
-      // of its jobs, so it does not launch phases that have no work
+      // one graph per (grid size, radix passes, backward) combination,
+      // captured once; a batch replays the one that covers the most passes
+      // and the backward of its jobs, so it does not launch phases that have
+      // no work, with small grids when all its phases have few units
+      for (int gs = 0; gs < 2; ++gs)
       for (int np = 1; np <= kServePasses; ++np) {
         for (int bwd = 0; bwd < 2; ++bwd) {
           if ((e = hipStreamBeginCapture(x.stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
             return fail_hip(e, "hipStreamBeginCapture");
-          enqueue_phases(x.dtab, x.stream, cus, np, bwd != 0);
+          enqueue_phases(x.dtab, x.stream, cus, np, bwd != 0, gs == 1);
           hipGraph_t graph = nullptr;
           e = hipStreamEndCapture(x.stream, &graph);
           if (e != hipSuccess) return fail_hip(e, "hipStreamEndCapture");
-          hipGraphExec_t& ge = x.exec[np - 1][bwd];
+          hipGraphExec_t& ge = x.exec[gs][np - 1][bwd];
           e = hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0);
           hipGraphDestroy(graph);
           if (e != hipSuccess) return fail_hip(e, "hipGraphInstantiate");
@@ -252,9 +268,10 @@ class GpuExecutor {
     for (int c = 0; c < kContexts; ++c) {
       Ctx& x = ctx_[c];
       if (x.stream) hipStreamSynchronize(x.stream);
-      for (auto& row : x.exec)
-        for (hipGraphExec_t ge : row)
-          if (ge) hipGraphExecDestroy(ge);
+      for (auto& grid : x.exec)
+        for (auto& row : grid)
+          for (hipGraphExec_t ge : row)
+            if (ge) hipGraphExecDestroy(ge);
       if (x.done) hipEventDestroy(x.done);
       if (x.stream) hipStreamDestroy(x.stream);
       if (x.htab) hipHostFree(x.htab);
@@ -304,17 +321,26 @@ class GpuExecutor {
       u[PH_BSIG] = bwd && !g.per_point && r.grad_sigma ? 1 : 0;
       for (int ph = 0; ph < PH_COUNT; ++ph) T->units[ph][i + 1] = T->units[ph][i] + u[ph];
     }
-    // the batch starts after every event its requests were submitted with
+    // the batch starts after every event its requests were submitted with;
+    // an event that has already completed needs no device-side wait (a wait
+    // on another stream's event costs the batch far more than the query)
     hipError_t e;
     for (int i = 0; i < nj; ++i) {
       if (!jobs[i]->req.r.ready) continue;
-      e = hipStreamWaitEvent(x.stream, static_cast<hipEvent_t>(jobs[i]->req.r.ready), 0);
+      hipEvent_t ev = static_cast<hipEvent_t>(jobs[i]->req.r.ready);
+      e = hipEventQuery(ev);
+      if (e == hipSuccess) continue;
+      if (e != hipErrorNotReady) return fail_hip(e, "hipEventQuery(ready)");
+      e = hipStreamWaitEvent(x.stream, ev, 0);
       if (e != hipSuccess) return fail_hip(e, "hipStreamWaitEvent(ready)");
     }
     const size_t bytes = offsetof(JobTable, view) + sizeof(ImageView) * (size_t)nj;
     e = hipMemcpyAsync(x.dtab, T, bytes, hipMemcpyHostToDevice, x.stream);
     if (e != hipSuccess) return fail_hip(e, "hipMemcpyAsync(table)");
-    e = hipGraphLaunch(x.exec[need_passes - 1][need_bwd ? 1 : 0], x.stream);
+    int most = 0;
+    for (int ph = 0; ph < PH_COUNT; ++ph) most = std::max(most, T->units[ph][nj]);
+    const int gs = most <= kSmallUnits ? 1 : 0;
+    e = hipGraphLaunch(x.exec[gs][need_passes - 1][need_bwd ? 1 : 0], x.stream);
     if (e != hipSuccess) return fail_hip(e, "hipGraphLaunch");
     e = hipEventRecord(x.done, x.stream);
     if (e != hipSuccess) return fail_hip(e, "hipEventRecord");
@@ -337,7 +363,7 @@ class GpuExecutor {
     JobTable* htab = nullptr;
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    hipGraphExec_t exec[kServePasses][2] = {};  // [radix passes - 1][backward]
+    hipGraphExec_t exec[2][kServePasses][2] = {};  // [small grids][radix passes - 1][backward]
   };
   int device_ = 0;
   void* arena_ = nullptr;

@@ -6,13 +6,14 @@
     ...
     res = srv.result(t)   # None while queued/running; dict when done
 
-Every request is one image (B = 1) with C <= 4 channels.  submit records an
-event on torch's current stream after the request's outputs are allocated,
-and the batch that runs the request waits for it on the device, so inputs
-produced by earlier work on that stream (and output memory the caching
-allocator hands back) are safe to use without a host synchronisation.  The
-binding keeps every tensor of a request, and the event, alive until its
-result has been collected.
+Every request is one image (B = 1) with C <= 4 channels.  When torch's
+current stream still has work queued, submit records an event on it after
+the request's outputs are allocated, and the batch that runs the request
+waits for it on the device, so inputs produced by earlier work on that
+stream (and output memory the caching allocator hands back) are safe to use
+without a host synchronisation; an idle stream needs no event.  The binding
+keeps every tensor of a request, and the event, alive until its result has
+been collected.
 """
 from __future__ import annotations
 
@@ -36,12 +37,24 @@ class Server:
         self._h = h
         self._device = torch.device("cuda", dev)
         self._live: Dict[int, dict] = {}
+        # Events that order each request after the caller's stream, created
+        # here and reused: creating a HIP event per request occasionally
+        # stalls for milliseconds (the runtime allocates events in batches).
+        self._events = [self._new_event() for _ in range(256)]
+
+    def _new_event(self) -> torch.cuda.Event:
+        e = torch.cuda.Event()
+        e.record(torch.cuda.current_stream(self._device))  # creates the HIP event now
+        return e
 
     def submit(self, pos, sigma, values, H: int, W: int, radius: float = 3.0, tile: int = 8,
                grad_out: Optional[torch.Tensor] = None, grads=("pos", "sigma", "values"),
-               out: Optional[torch.Tensor] = None, grad_buffers: Optional[dict] = None) -> int:
+               out: Optional[torch.Tensor] = None, grad_buffers: Optional[dict] = None,
+               after_stream: bool = True) -> int:
         """Queues one request.  out / grad_buffers ({"pos": t, "sigma": t,
-        "values": t}) may supply preallocated result tensors."""
+        "values": t}) may supply preallocated result tensors.  after_stream:
+        order the request after the work queued so far on torch's current
+        stream (False: the caller guarantees its inputs and buffers are ready)."""
         prob = problem(pos, sigma, values, H, W, radius, tile)
         if out is None:
             out = torch.empty((1, prob.C, prob.H, prob.W), dtype=torch.float32, device=self._device)
@@ -67,10 +80,16 @@ class Server:
             if "values" in grads:
                 keep["grad_values"] = gb["values"] if "values" in gb else torch.empty_like(values)
                 req.grad_values = keep["grad_values"].data_ptr()
-        ready = torch.cuda.Event()
-        ready.record(torch.cuda.current_stream(self._device))
-        keep["ready"] = ready
-        req.ready = ready.cuda_event
+        stream = torch.cuda.current_stream(self._device)
+        # An idle stream needs no event: its work is done.  (An event recorded
+        # on it would be one more marker on a hardware queue that the
+        # runtime may share with a server stream, which would then order the
+        # request behind another batch.)
+        if after_stream and not stream.query():
+            ready = self._events.pop() if self._events else self._new_event()
+            ready.record(stream)
+            keep["ready"] = ready
+            req.ready = ready.cuda_event
         ticket = ctypes.c_uint64()
         _lib.check("interp_submit", _lib.lib().interp_submit(self._h, ctypes.byref(req),
                                                              ctypes.byref(ticket)))
@@ -89,6 +108,8 @@ class Server:
         if st.state in (_lib.QUEUED, _lib.RUNNING):
             return None
         keep = self._live.pop(ticket)
+        if "ready" in keep:
+            self._events.append(keep["ready"])  # the server no longer waits on it
         res = {k: v for k, v in keep.items() if k == "out" or k.startswith("grad_")}
         res.pop("grad_out", None)
         res.update(state=st.state, err=st.err, t_submit_ns=st.t_submit_ns,
