@@ -1194,9 +1194,25 @@ __device__ inline void bwd_point(const ImageView& v, int unit, float* red4, int*
       else v.grad_sigma[j] = gsig;
     }
     if (v.grad_values) {
+      // the point's values' gradient is one scattered store where it can be
+      // (a float32 vector of C = 2..4 elements needs only 4-byte alignment)
+      if constexpr (ST == INTERP_STORAGE_F32 && NC >= 2 && NC <= 4) {
+        typedef float vnu __attribute__((ext_vector_type(NC), aligned(4)));
+        if (v.C == NC) {
+          vnu x;
 #pragma unroll
-      for (int k = 0; k < NC; ++k)
-        if (k < v.C) Val<ST>::store(v.grad_values, (size_t)j * v.C + k, gc[k]);
+          for (int k = 0; k < NC; ++k) x[k] = gc[k];
+          *reinterpret_cast<vnu*>(v.grad_values + (size_t)j * NC) = x;
+        } else {
+#pragma unroll
+          for (int k = 0; k < NC; ++k)
+            if (k < v.C) v.grad_values[(size_t)j * v.C + k] = gc[k];
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < NC; ++k)
+          if (k < v.C) Val<ST>::store(v.grad_values, (size_t)j * v.C + k, gc[k]);
+      }
     }
   }
   if (!v.per_point && v.grad_sigma) {
