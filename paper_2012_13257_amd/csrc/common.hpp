@@ -172,7 +172,9 @@ inline std::string make_geometry(const interp_problem* p, Geometry* g) {
   g->nb = g->nbx * g->nby;
   g->CT = channel_template(p->C + norm);
   g->CS = col_stride(p->C + norm);
-  g->CP = pix_stride(p->C + norm);
+  // pixel records hold a gradient slot per channel (not for the density
+  // factor's slot) and beta
+  g->CP = (g->CT - norm + 1 + 3) / 4 * 4;
   g->radius = p->radius;
   g->per_point = p->sigma_per_point;
   g->kern = p->kernel;

@@ -986,7 +986,7 @@ __device__ inline void bwd_point(const ImageView& v, int unit, float* red4, int*
   constexpr int CS = CT < 4 ? 4 : CT;
   constexpr bool kD = kDiagonal<KV>, kN = kNormalized<KV>;
   constexpr int NC = kN ? CT - 1 : CT;  // channel slots (the last is the density factor)
-  constexpr int CP = (CT + 1 + 3) / 4 * 4;
+  constexpr int CP = (NC + 1 + 3) / 4 * 4;  // pixel record: G'_0..G'_{NC-1}, beta
   constexpr int CP4 = CP / 4;
   int* order = lds;            // [256] local point index by regrouped slot
   int* cls_n = lds + 256;      // [32]
@@ -1118,9 +1118,9 @@ __device__ inline void bwd_point(const ImageView& v, int unit, float* red4, int*
           float w = __builtin_amdgcn_exp2f(d2 * (kD ? kHalfLog2e : g.z));
           w = (d2 <= (kD ? v.r2 : g.w)) ? w : 0.0f;
           if constexpr (kN) w *= zeta;
-          float A = -rec[CT];
+          float A = -rec[NC];
 #pragma unroll
-          for (int k = 0; k < CT; ++k) A = __builtin_fmaf(rec[k], cc[k], A);
+          for (int k = 0; k < NC; ++k) A = __builtin_fmaf(rec[k], cc[k], A);
 #pragma unroll
           for (int k = 0; k < NC; ++k) gc[k] = __builtin_fmaf(w, rec[k], gc[k]);
           const float tA = A * w;

@@ -143,9 +143,9 @@ __global__ __launch_bounds__(256) void k_forward(ImageView v0, int tiles_per_ima
   dev::forward_tile<CT, KV, ST>(image_of(v0, b), t - b * tiles_per_image, s_geo, s_col);
 }
 
-template <int CT, int ST>
+template <int NP, int ST>
 __global__ __launch_bounds__(256) void k_bwd_pixel(ImageView v0) {
-  dev::bwd_pixel<CT, ST>(image_of(v0, blockIdx.y), blockIdx.x);
+  dev::bwd_pixel<NP, ST>(image_of(v0, blockIdx.y), blockIdx.x);
 }
 
 // The dispatcher hands workgroup i to XCD i % 8; units of 256 sorted points
@@ -201,7 +201,9 @@ template <int CT, int KV, int ST>
 hipError_t launch_backward_t(const Geometry& g, const ImageView& v0, hipStream_t st) {
   {
     ProfRange pr_("bwd_pixel", st);
-    hipLaunchKernelGGL((k_bwd_pixel<CT, ST>), dim3(cdiv((long long)g.H * g.W, 256), g.B), dim3(256), 0,
+    // gradient slots of the pixel record: the density factor's slot has none
+    constexpr int NP = (KV & INTERP_KERNEL_NORMALIZED) ? CT - 1 : CT;
+    hipLaunchKernelGGL((k_bwd_pixel<NP, ST>), dim3(cdiv((long long)g.H * g.W, 256), g.B), dim3(256), 0,
                        st, v0);
   }
   if (g.N > 0) {
