@@ -2,6 +2,8 @@
 the same inputs (bitwise) whether it runs alone or inside a mix of requests
 of other sizes and channel counts; results also match the oracle; budget and
 argument errors are reported."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -158,6 +160,23 @@ def test_server_budget_and_argument_errors():
         with pytest.raises(_lib.InterpError) as e:
             srv.submit(p5, s5, v5, 16, 16)
         assert e.value.code == _lib.INTERP_EINVAL
+        # float32 storage only on the serving path
+        with pytest.raises(_lib.InterpError) as e:
+            srv.submit(p5, s5, v5[:, :, :4].to(torch.bfloat16).contiguous(), 16, 16)
+        assert e.value.code == _lib.INTERP_EINVAL
+        # and the plain isotropic kernel only
+        from paper_2012_13257_amd import interp
+        v4 = v5[:, :, :4].contiguous()
+        o4 = torch.empty((1, 4, 16, 16), device="cuda")
+        for kern in (_lib.KERNEL_NORMALIZED, _lib.KERNEL_DIAGONAL):
+            req = _lib.Request()
+            req.prob = interp.problem(p5, s5, v4, 16, 16)
+            req.prob.kernel = kern
+            req.pos, req.sigma, req.values, req.out = (p5.data_ptr(), s5.data_ptr(),
+                                                       v4.data_ptr(), o4.data_ptr())
+            ticket = ctypes.c_uint64()
+            rc = _lib.lib().interp_submit(srv._h, ctypes.byref(req), ctypes.byref(ticket))
+            assert rc == _lib.INTERP_EINVAL, kern
         # the server still serves valid requests afterwards
         t = srv.submit(p5[:, :, :], s5, v5[:, :, :4].contiguous(), 16, 16)
         assert srv.drain(30000)
