@@ -162,8 +162,8 @@ def time_steps(fn, steps: int, warmup: int, profile: bool):
     ms = start.elapsed_time(stop) / steps
     kernels = {}
     if profile:
-        for name in ("bin_keys", "radix_hist", "radix_scan", "radix_scatter", "bin_finish",
-                     "fwd_plan", "forward", "bwd_pixel", "bwd_point", "bwd_sigma_sum"):
+        for name in ("bin_keys", "radix_hist", "radix_scan", "radix_scatter", "place_wide",
+                     "bin_finish", "fwd_plan", "forward", "bwd_pixel", "bwd_point", "bwd_sigma_sum"):
             tot, n = _lib.profile_read(name)
             if n:
                 kernels[name] = {"avg_us": 1000.0 * tot / n, "launches": n}
@@ -704,8 +704,8 @@ def main():
                             "alu_frac": round(a / VALU_PEAK_TLANEOPS, 4),
                             "alu_frac_impl": round(a * im / m / VALU_PEAK_TLANEOPS, 4)}
     binning = sum(kernels[k]["avg_us"] * kernels[k]["launches"] / args.steps
-                  for k in ("bin_keys", "radix_hist", "radix_scan", "radix_scatter", "bin_finish",
-                            "fwd_plan") if k in kernels)
+                  for k in ("bin_keys", "radix_hist", "radix_scan", "radix_scatter", "place_wide",
+                            "bin_finish", "fwd_plan") if k in kernels)
     del out, saved, work, gp, gs, gv, G, graph, graph_fwd, ref
     torch.cuda.empty_cache()
 

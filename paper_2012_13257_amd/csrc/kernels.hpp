@@ -442,13 +442,20 @@ __device__ inline void radix_scatter(const ImageView& v, int p, int tile, int* l
     }
   }
   if (kWide && last) {
+    // wide records are placed afterwards by place_wide, which reads the
+    // inputs in point order: here the inverse permutation, in the index
+    // buffer this pass does not use
+    int* const iperm = out_a ? vA : vB;
 #pragma unroll
     for (int q = 0; q < kRadixItems; ++q) {
-      eg[q] = point_geo(v, ej[q]);
-      ec[q] = point_values4<ST>(v, ej[q], 0);
+      if (t + q * 256 < tn) {
+        const int g = epos[q];
+        keysF[g] = ek[q];
+        perm[g] = ej[q];
+        iperm[ej[q]] = g;
+      }
     }
-  }
-  if (last) {
+  } else if (last) {
 #pragma unroll
     for (int q = 0; q < kRadixItems; ++q) {
       if (t + q * 256 < tn) {
@@ -474,23 +481,27 @@ __device__ inline void radix_scatter(const ImageView& v, int p, int tile, int* l
       }
     }
   }
-  if constexpr (kWide) {  // values beyond the first four (CS <= 32: at most 7 more float4s)
-    if (last) {
-      constexpr int kExtra = 7;
-      for (int q = 0; q < kRadixItems; ++q) {
-        if (t + q * 256 >= tn) continue;
-        float4 x[kExtra];
-#pragma unroll
-        for (int r = 0; r < kExtra; ++r)
-          if (4 * (r + 1) < v.CS) x[r] = point_values4<ST>(v, ej[q], 4 * (r + 1));
-        const size_t g4 = (size_t)epos[q] * (v.CS / 4);
-#pragma unroll
-        for (int r = 0; r < kExtra; ++r)
-          if (4 * (r + 1) < v.CS) Val<ST>::store4(col, g4 + r + 1, x[r]);
-      }
-    }
-  }
   __syncthreads();
+}
+
+// unit = 256 points in point order, after the last radix pass of wide
+// records: each point's sorted record (geo, and the values padded to CS) is
+// built from coalesced reads of the inputs and written to its sorted place
+// (iperm: the inverse permutation the last pass left in the index buffer it
+// did not use).  Gathering the records in sorted order instead reads every
+// point's inputs from a random place, a cache line per piece.
+// unit = 64 points, four lanes per point: lane k of a point writes its
+// values' groups of four k, k + 4, ..., so that one store instruction writes
+// whole 64-byte pieces of the sorted records.
+template <int ST = INTERP_STORAGE_F32>
+__device__ inline void place_wide(const ImageView& v, int unit) {
+  const int j = unit * 64 + (threadIdx.x >> 2), k = threadIdx.x & 3;
+  if (j >= v.N) return;
+  const int* iperm = ((v.npass - 1) & 1) == 0 ? v.vA : v.vB;
+  const int g = iperm[j];
+  if (k == 0) v.geo[g] = point_geo(v, j);
+  for (int c = 4 * k; c < v.CS; c += 16)
+    Val<ST>::store4(v.col, (size_t)g * (v.CS / 4) + c / 4, point_values4<ST>(v, j, c));
 }
 
 // unit = 256 sorted positions (N + 1 positions in all): bin offsets from the
@@ -927,8 +938,10 @@ __device__ inline void forward_block_q(const ImageView& v, int unit, int mode, f
 // ---------------------------------------------------------------------------
 
 // unit = 256 pixels: G'_ik = G_ik / Z_i and beta_i = sum_k G_ik out_ik / Z_i,
-// packed per pixel as (G'_0 .. G'_{CT-1}, beta, zero padding)
-template <int CT, int ST = INTERP_STORAGE_F32>
+// packed per pixel as (G'_0 .. G'_{CT-1}, beta, zero padding).  Interleaved
+// ([H*W][CP]) for the one-lane-per-point adjoint; planar ([CP/4][H*W] groups
+// of four values) for the eight-lanes-per-point adjoint of many channels.
+template <int CT, int ST = INTERP_STORAGE_F32, bool kPlanar = false>
 __device__ inline void bwd_pixel(const ImageView& v, int unit) {
   constexpr int CP = (CT + 1 + 3) / 4 * 4;
   const int HW = v.H * v.W;
@@ -952,10 +965,17 @@ __device__ inline void bwd_pixel(const ImageView& v, int unit) {
     }
     rec[CT] = beta * a;
   }
-  float4* dst = reinterpret_cast<float4*>(v.prec + (size_t)i * CP);
+  if constexpr (kPlanar) {
+    float4* dst = reinterpret_cast<float4*>(v.prec) + i;
 #pragma unroll
-  for (int q = 0; q < CP / 4; ++q)
-    dst[q] = make_float4(rec[4 * q], rec[4 * q + 1], rec[4 * q + 2], rec[4 * q + 3]);
+    for (int q = 0; q < CP / 4; ++q)
+      dst[(size_t)q * HW] = make_float4(rec[4 * q], rec[4 * q + 1], rec[4 * q + 2], rec[4 * q + 3]);
+  } else {
+    float4* dst = reinterpret_cast<float4*>(v.prec + (size_t)i * CP);
+#pragma unroll
+    for (int q = 0; q < CP / 4; ++q)
+      dst[q] = make_float4(rec[4 * q], rec[4 * q + 1], rec[4 * q + 2], rec[4 * q + 3]);
+  }
 }
 
 // Pixel records a workgroup of the adjoint can stage in LDS (36 KB).
@@ -1226,6 +1246,186 @@ __device__ inline void bwd_point(const ImageView& v, int unit, float* red4, int*
       gs_l[lp] = gsig2;
       __syncthreads();
       const float s2 = block_sum(gs_l[threadIdx.x], red4);
+      if (threadIdx.x == 0) v.gpart[2 * unit + 1] = s2;
+    }
+  }
+}
+
+// Adjoint for eight or more value slots (CT >= 8).  One lane per point
+// would read a whole pixel record (CP values) per pixel from a different
+// place in every lane; here eight lanes share a point instead: a wavefront
+// takes eight points at a time, lane group g = lane / 8 on one point and
+// lane l = lane % 8 on columns l, l + 8, ... of each row of its disk, so
+// that the group reads eight neighbouring pixels -- one 128-byte line per
+// group of four values of the planar pixel records.  A round of the
+// workgroup takes 32 consecutive points of the unit (in sorted order, so
+// their disks overlap and share records in the caches), ordered by disk
+// size among themselves.  The test and the
+// weight per pixel are the one-lane kernel's, bit for bit; a group's partial
+// sums are combined by an xor butterfly over its eight lanes (every lane
+// ends with the same bits) and its lanes write the point's results.  gs_l,
+// gs2_l: 256 floats each.
+template <int CT, int KV = 0, int ST = INTERP_STORAGE_F32>
+__device__ inline void bwd_point_wide(const ImageView& v, int unit, float* red4, float* gs_l,
+                                      float* gs2_l, int* cls_l, int* order) {
+  static_assert(CT >= 8, "eight lanes per point pay off for wide records only");
+  constexpr int CS = CT;
+  constexpr bool kD = kDiagonal<KV>, kN = kNormalized<KV>;
+  constexpr int NC = kN ? CT - 1 : CT;
+  constexpr int CP = (NC + 1 + 3) / 4 * 4;
+  constexpr int CP4 = CP / 4;
+  const int base = unit * 256;
+  // within each round of 32 consecutive points, the points in order of disk
+  // size (class of half a pixel of extent, ties by position), so that the
+  // eight points of a wavefront loop over similar extents
+  {
+    const int tt = base + threadIdx.x;
+    int cls = 0;
+    if (tt < v.N) {
+      const float4 gg = v.geo[tt];
+      const float ext = kD ? v.radius / fmaxf(fminf(gg.z, gg.w), 1e-30f) : sqrtf(fmaxf(gg.w, 0.0f));
+      cls = (int)fminf(2.0f * ext, 1e6f);
+    }
+    cls_l[threadIdx.x] = cls;
+    __syncthreads();
+    const int r0 = threadIdx.x & ~31, me = threadIdx.x & 31;
+    int rank = 0;
+    for (int k = 0; k < 32; ++k) {
+      const int ck = cls_l[r0 + k];
+      rank += (ck < cls || (ck == cls && k < me)) ? 1 : 0;
+    }
+    order[r0 + rank] = threadIdx.x;
+    __syncthreads();
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int grp = lane >> 3, l = lane & 7;
+  const size_t HW = (size_t)v.H * v.W;
+  const float4* prec4 = reinterpret_cast<const float4*>(v.prec);
+  for (int r = 0; r < 8; ++r) {
+    const int lp = order[r * 32 + wid * 8 + grp];
+    const int t = base + lp;
+    if (t >= v.N) continue;
+    const float4 g = v.geo[t];
+    float cc[CT];
+#pragma unroll
+    for (int q = 0; q < CT / 4; ++q) {
+      const float4 c4 = Val<ST>::load4(v.col, (size_t)t * (CS / 4) + q);
+      cc[4 * q] = c4.x; cc[4 * q + 1] = c4.y; cc[4 * q + 2] = c4.z; cc[4 * q + 3] = c4.w;
+    }
+    const float zeta = kN ? cc[CT - 1] : 1.0f;
+    const int j = v.perm[t];
+    const float2 sg = sigma2_of(v, j);
+    const float Rh = conservative_reach(__fmul_rn(v.radius, sg.y));  // along y
+    const float fvlo = fminf(fmaxf(ceilf(g.y - Rh), 0.0f), (float)v.H);
+    const float fvhi = fmaxf(fminf(floorf(g.y + Rh), (float)(v.H - 1)), -1.0f);
+    const int vlo = (int)fvlo, vhi = (int)fvhi;
+    float gx = 0.0f, gy = 0.0f, gs = 0.0f, gs2 = 0.0f, ga = 0.0f;
+    float gc[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) gc[k] = 0.0f;
+    const float R2m = (kD ? v.r2 : g.w) * (1.0f + 0x1p-20f);
+    for (int py = vlo; py <= vhi; ++py) {
+      const float dy = (float)py - g.y;
+      const float qy = kD ? dy * g.w : dy;
+      const float dyy = qy * qy;
+      const float rr = __builtin_amdgcn_sqrtf(fmaxf(R2m - dyy, 0.0f)) * (kD ? sg.x : 1.0f) *
+                           (1.0f + 0x1p-10f) + 0x1p-10f;
+      const int ulo = (int)fminf(fmaxf(ceilf(g.x - rr), 0.0f), (float)v.W);
+      const int uhi = (int)fmaxf(fminf(floorf(g.x + rr), (float)(v.W - 1)), -1.0f);
+      const float4* rowp = prec4 + (size_t)py * v.W;
+      for (int s = ulo; s <= uhi; s += 8) {
+        const int px = s + l;
+        const bool inside = px <= uhi;  // columns past the chord are outside the radius
+        const int pxc = min(px, uhi);   // or outside the image: no load beyond the row
+        float rec[CP];
+#pragma unroll
+        for (int q = 0; q < CP4; ++q) {
+          const float4 r4 = rowp[(size_t)q * HW + pxc];
+          rec[4 * q] = r4.x; rec[4 * q + 1] = r4.y; rec[4 * q + 2] = r4.z; rec[4 * q + 3] = r4.w;
+        }
+        const float dx = (float)px - g.x;
+        const float qx = kD ? dx * g.z : dx;
+        const float qxx = qx * qx;
+        const float d2 = qxx + dyy;
+        float w = __builtin_amdgcn_exp2f(d2 * (kD ? kHalfLog2e : g.z));
+        w = (inside && d2 <= (kD ? v.r2 : g.w)) ? w : 0.0f;
+        if constexpr (kN) w *= zeta;
+        float A = -rec[NC];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) A = __builtin_fmaf(rec[k], cc[k], A);
+#pragma unroll
+        for (int k = 0; k < NC; ++k) gc[k] = __builtin_fmaf(w, rec[k], gc[k]);
+        const float tA = A * w;
+        gx = __builtin_fmaf(tA, qx, gx);
+        gy = __builtin_fmaf(tA, qy, gy);
+        if constexpr (kD) {
+          gs = __builtin_fmaf(tA, qxx, gs);
+          gs2 = __builtin_fmaf(tA, dyy, gs2);
+        } else {
+          gs = __builtin_fmaf(tA, d2, gs);
+        }
+        if constexpr (kN) ga += tA;
+      }
+    }
+    // the group's sums (xor butterfly: every lane of the group ends with the
+    // same bits)
+    auto gsum = [](float x) {
+      x += __shfl_xor(x, 1);
+      x += __shfl_xor(x, 2);
+      x += __shfl_xor(x, 4);
+      return x;
+    };
+#pragma unroll
+    for (int k = 0; k < NC; ++k) gc[k] = gsum(gc[k]);
+    gx = gsum(gx);
+    gy = gsum(gy);
+    gs = gsum(gs);
+    if constexpr (kD) gs2 = gsum(gs2);
+    if constexpr (kN) ga = gsum(ga);
+    float2 gp;
+    float gsig, gsig2 = 0.0f;
+    if constexpr (kD) {
+      gp = make_float2(gx * g.z, gy * g.w);
+      gsig = (kN ? gs - ga : gs) * g.z;
+      gsig2 = (kN ? gs2 - ga : gs2) * g.w;
+    } else {
+      const float inv_s2 = 1.0f / (sg.x * sg.x);
+      gp = make_float2(gx * inv_s2, gy * inv_s2);
+      gsig = gs * inv_s2 / sg.x;
+      if constexpr (kN) gsig -= 2.0f * ga / sg.x;
+    }
+    if (l == 0) {
+      if (v.grad_pos) reinterpret_cast<float2*>(v.grad_pos)[j] = gp;
+      if (v.grad_sigma && v.per_point) {
+        if constexpr (kD) reinterpret_cast<float2*>(v.grad_sigma)[j] = make_float2(gsig, gsig2);
+        else v.grad_sigma[j] = gsig;
+      }
+      gs_l[lp] = gsig;
+      gs2_l[lp] = gsig2;
+    }
+    if (v.grad_values) {
+      // lane l writes channels l, l + 8, ...: eight consecutive values of
+      // the point per store
+#pragma unroll
+      for (int m = 0; m < (NC + 7) / 8; ++m) {
+        float x = gc[8 * m];
+#pragma unroll
+        for (int kk = 1; kk < 8; ++kk)
+          if (8 * m + kk < NC) x = l == kk ? gc[8 * m + kk] : x;
+        const int k = 8 * m + l;
+        if (k < NC && k < v.C) Val<ST>::store(v.grad_values, (size_t)j * v.C + k, x);
+      }
+    }
+  }
+  if (!v.per_point && v.grad_sigma) {
+    // the shared sigma's derivative: per-unit partial sums in point order
+    // (points beyond N contribute nothing)
+    __syncthreads();
+    const bool own = base + (int)threadIdx.x < v.N;
+    const float s = block_sum(own ? gs_l[threadIdx.x] : 0.0f, red4);
+    if (threadIdx.x == 0) v.gpart[2 * unit] = s;
+    if constexpr (kD) {
+      const float s2 = block_sum(own ? gs2_l[threadIdx.x] : 0.0f, red4);
       if (threadIdx.x == 0) v.gpart[2 * unit + 1] = s2;
     }
   }

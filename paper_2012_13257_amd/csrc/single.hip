@@ -45,6 +45,11 @@ __global__ __launch_bounds__(256) void k_radix_scatter(ImageView v0, int p, int 
   dev::radix_scatter<kWide, ST>(image_of(v0, blockIdx.y), p, tile, lds);
 }
 
+template <int ST>
+__global__ __launch_bounds__(256) void k_place_wide(ImageView v0) {
+  dev::place_wide<ST>(image_of(v0, blockIdx.y), blockIdx.x);
+}
+
 // also clears the counters of the forward's work order (fplan, 64 ints)
 __global__ __launch_bounds__(256) void k_bin_finish(ImageView v0, int* fplan) {
   __shared__ float red4[4];
@@ -143,9 +148,9 @@ __global__ __launch_bounds__(256) void k_forward(ImageView v0, int tiles_per_ima
   dev::forward_tile<CT, KV, ST>(image_of(v0, b), t - b * tiles_per_image, s_geo, s_col);
 }
 
-template <int NP, int ST>
+template <int NP, int ST, bool kPlanar>
 __global__ __launch_bounds__(256) void k_bwd_pixel(ImageView v0) {
-  dev::bwd_pixel<NP, ST>(image_of(v0, blockIdx.y), blockIdx.x);
+  dev::bwd_pixel<NP, ST, kPlanar>(image_of(v0, blockIdx.y), blockIdx.x);
 }
 
 // The dispatcher hands workgroup i to XCD i % 8; units of 256 sorted points
@@ -160,6 +165,16 @@ __global__ __launch_bounds__(256) void k_bwd_point(ImageView v0, int per8) {
   const int unit = (blockIdx.x & 7) * per8 + (blockIdx.x >> 3);
   if ((int)(blockIdx.x >> 3) >= per8 || unit >= v0.units256) return;
   dev::bwd_point<CT, KV, ST>(image_of(v0, blockIdx.y), unit, red4, lds, stage);
+}
+
+template <int CT, int KV, int ST>
+__global__ __launch_bounds__(256) void k_bwd_point_wide(ImageView v0, int per8) {
+  __shared__ float red4[4];
+  __shared__ float gs_l[256], gs2_l[256];
+  __shared__ int cls_l[256], order[256];
+  const int unit = (blockIdx.x & 7) * per8 + (blockIdx.x >> 3);
+  if ((int)(blockIdx.x >> 3) >= per8 || unit >= v0.units256) return;
+  dev::bwd_point_wide<CT, KV, ST>(image_of(v0, blockIdx.y), unit, red4, gs_l, gs2_l, cls_l, order);
 }
 
 __global__ __launch_bounds__(256) void k_bwd_sigma_sum(ImageView v0) {
@@ -202,14 +217,20 @@ hipError_t launch_backward_t(const Geometry& g, const ImageView& v0, hipStream_t
   {
     ProfRange pr_("bwd_pixel", st);
     // gradient slots of the pixel record: the density factor's slot has none
+    // (planar records for the eight-lanes-per-point adjoint of CT >= 8)
     constexpr int NP = (KV & INTERP_KERNEL_NORMALIZED) ? CT - 1 : CT;
-    hipLaunchKernelGGL((k_bwd_pixel<NP, ST>), dim3(cdiv((long long)g.H * g.W, 256), g.B), dim3(256), 0,
-                       st, v0);
+    hipLaunchKernelGGL((k_bwd_pixel<NP, ST, (CT >= 8)>), dim3(cdiv((long long)g.H * g.W, 256), g.B),
+                       dim3(256), 0, st, v0);
   }
   if (g.N > 0) {
     ProfRange pr_("bwd_point", st);
     const int per8 = (g.units256 + 7) / 8;
-    hipLaunchKernelGGL((k_bwd_point<CT, KV, ST>), dim3(8 * per8, g.B), dim3(256), 0, st, v0, per8);
+    if constexpr (CT >= 8)
+      hipLaunchKernelGGL((k_bwd_point_wide<CT, KV, ST>), dim3(8 * per8, g.B), dim3(256), 0, st, v0,
+                         per8);
+    else
+      hipLaunchKernelGGL((k_bwd_point<CT, KV, ST>), dim3(8 * per8, g.B), dim3(256), 0, st, v0,
+                         per8);
   }
   if (!g.per_point && v0.grad_sigma) {
     ProfRange pr_("bwd_sigma_sum", st);
@@ -277,6 +298,10 @@ hipError_t launch_binning(const Geometry& g, const ImageView& v0, int* fplan, hi
         hipLaunchKernelGGL((k_radix_scatter<false, ST>), dim3(8 * per8, g.B), dim3(256), 0, st,
                            v0, p, per8);
     }
+  }
+  if (g.CS > 4 && g.npass > 0 && g.N > 0) {
+    ProfRange pr_("place_wide", st);
+    hipLaunchKernelGGL((k_place_wide<ST>), dim3(cdiv(g.N, 64), g.B), dim3(256), 0, st, v0);
   }
   {
     ProfRange pr_("bin_finish", st);
