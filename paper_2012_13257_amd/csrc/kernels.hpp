@@ -1260,7 +1260,8 @@ __device__ inline void bwd_point(const ImageView& v, int unit, float* red4, int*
 // group of four values of the planar pixel records.  A round of the
 // workgroup takes 32 consecutive points of the unit (in sorted order, so
 // their disks overlap and share records in the caches), ordered by disk
-// size among themselves.  The test and the
+// size among themselves; rows are walked in pairs, one pixel of each per
+// trip, for two independent chains per lane.  The test and the
 // weight per pixel are the one-lane kernel's, bit for bit; a group's partial
 // sums are combined by an xor butterfly over its eight lanes (every lane
 // ends with the same bits) and its lanes write the point's results.  gs_l,
@@ -1324,47 +1325,73 @@ __device__ inline void bwd_point_wide(const ImageView& v, int unit, float* red4,
 #pragma unroll
     for (int k = 0; k < NC; ++k) gc[k] = 0.0f;
     const float R2m = (kD ? v.r2 : g.w) * (1.0f + 0x1p-20f);
-    for (int py = vlo; py <= vhi; ++py) {
+    // the chord of row py: columns [ulo, uhi] (conservative: the radius
+    // test decides), clipped to the image
+    auto chord = [&](int py, float* dyy_o, float* qy_o, int* ulo_o, int* uhi_o) {
       const float dy = (float)py - g.y;
       const float qy = kD ? dy * g.w : dy;
       const float dyy = qy * qy;
       const float rr = __builtin_amdgcn_sqrtf(fmaxf(R2m - dyy, 0.0f)) * (kD ? sg.x : 1.0f) *
                            (1.0f + 0x1p-10f) + 0x1p-10f;
-      const int ulo = (int)fminf(fmaxf(ceilf(g.x - rr), 0.0f), (float)v.W);
-      const int uhi = (int)fmaxf(fminf(floorf(g.x + rr), (float)(v.W - 1)), -1.0f);
+      *ulo_o = (int)fminf(fmaxf(ceilf(g.x - rr), 0.0f), (float)v.W);
+      *uhi_o = (int)fmaxf(fminf(floorf(g.x + rr), (float)(v.W - 1)), -1.0f);
+      *dyy_o = dyy;
+      *qy_o = qy;
+    };
+    // pixel (px, py) with its record read at column pxc of the row (pxc is
+    // px inside the chord; w = 0 when px is not)
+    auto pixel = [&](int py, int px, bool inside, int pxc, float dyy, float qy) {
       const float4* rowp = prec4 + (size_t)py * v.W;
-      for (int s = ulo; s <= uhi; s += 8) {
-        const int px = s + l;
-        const bool inside = px <= uhi;  // columns past the chord are outside the radius
-        const int pxc = min(px, uhi);   // or outside the image: no load beyond the row
-        float rec[CP];
+      float rec[CP];
 #pragma unroll
-        for (int q = 0; q < CP4; ++q) {
-          const float4 r4 = rowp[(size_t)q * HW + pxc];
-          rec[4 * q] = r4.x; rec[4 * q + 1] = r4.y; rec[4 * q + 2] = r4.z; rec[4 * q + 3] = r4.w;
-        }
-        const float dx = (float)px - g.x;
-        const float qx = kD ? dx * g.z : dx;
-        const float qxx = qx * qx;
-        const float d2 = qxx + dyy;
-        float w = __builtin_amdgcn_exp2f(d2 * (kD ? kHalfLog2e : g.z));
-        w = (inside && d2 <= (kD ? v.r2 : g.w)) ? w : 0.0f;
-        if constexpr (kN) w *= zeta;
-        float A = -rec[NC];
+      for (int q = 0; q < CP4; ++q) {
+        const float4 r4 = rowp[(size_t)q * HW + pxc];
+        rec[4 * q] = r4.x; rec[4 * q + 1] = r4.y; rec[4 * q + 2] = r4.z; rec[4 * q + 3] = r4.w;
+      }
+      const float dx = (float)px - g.x;
+      const float qx = kD ? dx * g.z : dx;
+      const float qxx = qx * qx;
+      const float d2 = qxx + dyy;
+      float w = __builtin_amdgcn_exp2f(d2 * (kD ? kHalfLog2e : g.z));
+      w = (inside && d2 <= (kD ? v.r2 : g.w)) ? w : 0.0f;
+      if constexpr (kN) w *= zeta;
+      float A = -rec[NC];
 #pragma unroll
-        for (int k = 0; k < NC; ++k) A = __builtin_fmaf(rec[k], cc[k], A);
+      for (int k = 0; k < NC; ++k) A = __builtin_fmaf(rec[k], cc[k], A);
 #pragma unroll
-        for (int k = 0; k < NC; ++k) gc[k] = __builtin_fmaf(w, rec[k], gc[k]);
-        const float tA = A * w;
-        gx = __builtin_fmaf(tA, qx, gx);
-        gy = __builtin_fmaf(tA, qy, gy);
-        if constexpr (kD) {
-          gs = __builtin_fmaf(tA, qxx, gs);
-          gs2 = __builtin_fmaf(tA, dyy, gs2);
-        } else {
-          gs = __builtin_fmaf(tA, d2, gs);
-        }
-        if constexpr (kN) ga += tA;
+      for (int k = 0; k < NC; ++k) gc[k] = __builtin_fmaf(w, rec[k], gc[k]);
+      const float tA = A * w;
+      gx = __builtin_fmaf(tA, qx, gx);
+      gy = __builtin_fmaf(tA, qy, gy);
+      if constexpr (kD) {
+        gs = __builtin_fmaf(tA, qxx, gs);
+        gs2 = __builtin_fmaf(tA, dyy, gs2);
+      } else {
+        gs = __builtin_fmaf(tA, d2, gs);
+      }
+      if constexpr (kN) ga += tA;
+    };
+    // rows in pairs: every trip evaluates one pixel of each row (two
+    // independent chains per lane) over the union of the two chords
+    for (int py = vlo; py <= vhi; py += 2) {
+      float dyyA, qyA, dyyB = 0.0f, qyB = 0.0f;
+      int uloA, uhiA, uloB = 1, uhiB = 0;
+      chord(py, &dyyA, &qyA, &uloA, &uhiA);
+      const bool hasB = py + 1 <= vhi;
+      if (hasB) chord(py + 1, &dyyB, &qyB, &uloB, &uhiB);
+      // an empty chord takes the other's start (no pixel of it is inside)
+      if (uloB > uhiB) { uloB = uloA; uhiB = uloA - 1; }
+      if (uloA > uhiA) { uloA = uloB; uhiA = uloB - 1; }
+      const int lo = min(uloA, uloB), hi = max(uhiA, uhiB);
+      const int rowB = hasB ? py + 1 : py;
+      for (int s0 = lo; s0 <= hi; s0 += 8) {
+        const int px = s0 + l;
+        const bool inA = px >= uloA && px <= uhiA, inB = px >= uloB && px <= uhiB;
+        // load columns inside the image: the chord's (or its start's)
+        const int pA = min(min(max(px, uloA), max(uhiA, uloA)), v.W - 1);
+        const int pB = min(min(max(px, uloB), max(uhiB, uloB)), v.W - 1);
+        pixel(py, px, inA, pA, dyyA, qyA);
+        pixel(rowB, px, inB, pB, dyyB, qyB);
       }
     }
     // the group's sums (xor butterfly: every lane of the group ends with the
