@@ -1355,9 +1355,12 @@ __device__ inline void bwd_point_wide(const ImageView& v, int unit, float* red4,
       float w = __builtin_amdgcn_exp2f(d2 * (kD ? kHalfLog2e : g.z));
       w = (inside && d2 <= (kD ? v.r2 : g.w)) ? w : 0.0f;
       if constexpr (kN) w *= zeta;
-      float A = -rec[NC];
+      // A in four partial chains (a 16-deep chain of dependent FMAs would
+      // leave the lane waiting on each result)
+      float Ap[4] = {-rec[NC], 0.0f, 0.0f, 0.0f};
 #pragma unroll
-      for (int k = 0; k < NC; ++k) A = __builtin_fmaf(rec[k], cc[k], A);
+      for (int k = 0; k < NC; ++k) Ap[k & 3] = __builtin_fmaf(rec[k], cc[k], Ap[k & 3]);
+      const float A = (Ap[0] + Ap[1]) + (Ap[2] + Ap[3]);
 #pragma unroll
       for (int k = 0; k < NC; ++k) gc[k] = __builtin_fmaf(w, rec[k], gc[k]);
       const float tA = A * w;
