@@ -36,14 +36,17 @@ def test_backward_cfg1_full():
     _full_backward_check(synth.config1())
 
 
-@pytest.mark.parametrize("C", [1, 3, 4, 8, 16])
+@pytest.mark.parametrize("C", [1, 3, 4, 8, 16, 32])
 def test_backward_per_point_sigma_multitile(C):
     _full_backward_check(synth.random_workload(700 + C, 2, 500, 26, 37, C=C, sigma=(0.5, 2.0),
                                                values="normal", blob_frac=0.5, blob_std=(2.0, 5.0)))
 
 
-def test_backward_shared_sigma_batch():
-    _full_backward_check(synth.random_workload(751, 3, 400, 24, 30, C=3, sigma=0.9))
+@pytest.mark.parametrize("C", [3, 12])
+def test_backward_shared_sigma_batch(C):
+    """Shared sigma: the per-unit partial sums of dL/dsigma and their
+    fixed-order total (C = 12 runs the eight-lanes-per-point adjoint)."""
+    _full_backward_check(synth.random_workload(751 + C, 3, 400, 24, 30, C=C, sigma=0.9))
 
 
 def _densest_bin_points(wl, b, k, tile=8):
