@@ -600,11 +600,24 @@ def main():
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the other workloads (64x64 latency, 16x256x256, 2x4096x4096 C=16)")
     ap.add_argument("--serving-requests", type=int, default=4096)
+    ap.add_argument("--workload", choices=("c16",), default=None,
+                    help="time only the 2 x 4096^2, C = 16 forward + backward (for profiling "
+                         "its kernels); prints that measurement instead of the benchmark line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.workload:
+        import torch
+        from paper_2012_13257_amd import synth
+        if not torch.cuda.is_available():
+            print("bench.py needs the ROCm device", file=sys.stderr)
+            sys.exit(1)
+        log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)  # noqa: E731
+        r = measure_workload(synth.config5(), args.steps, args.warmup, True, log)
+        print(json.dumps({"workload": "cfg5_2x4096x4096_n4M_c16_fwd_bwd", **r}), flush=True)
+        return
 
     import torch
     from paper_2012_13257_amd import interp, synth, _lib
