@@ -70,7 +70,7 @@ struct PhaseLds {
                               : (PH == PH_BPOINT)                 ? 256 + 64
                               : (PH >= PH_HIST0 && PH <= PH_HIST2) || PH == PH_KEYS ? 256
                                                                   : 4;
-  static constexpr int f4 = PH == PH_FWD ? dev::fwd_quarter_lds_f4()
+  static constexpr int f4 = PH == PH_FWD ? dev::fwd_quarter_lds_f4<4>()
                             : PH == PH_BPOINT ? dev::kBwdStageF4
                                               : 1;
 };

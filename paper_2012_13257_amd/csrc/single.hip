@@ -117,7 +117,7 @@ __global__ __launch_bounds__(256) void k_fwd_plan(ImageView v0, int units, int t
 template <int CT, int KV, int ST>
 __global__ __launch_bounds__(256) void k_forward_lpt(ImageView v0, int units, int total,
                                                      const int* fplan) {
-  __shared__ float4 s_rec[dev::fwd_quarter_lds_f4()];
+  __shared__ float4 s_rec[dev::fwd_quarter_lds_f4<CT>()];
   const int lane = threadIdx.x & 63;
   // lane l < 32: work items in the classes 31 .. 31 - l (heaviest first)
   int incl = lane < kPlanBuckets ? fplan[kPlanBuckets - 1 - lane] : 0;
