@@ -21,6 +21,8 @@ constexpr size_t kAlign = 256;
 constexpr int kRadixItems = 4;         // keys per thread in a radix pass
 constexpr int kRadixTile = 256 * kRadixItems;  // keys per workgroup in a radix pass
 constexpr int kRadixMaxPasses = 4;     // bin keys of up to 32 bits
+constexpr int kMaxDigits = 1024;       // digits of one radix pass (the single-call path sorts
+                                       // keys of up to 10 bits in one pass)
 
 inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
 
@@ -127,8 +129,8 @@ inline Layout make_layout(const Geometry& g) {
   L.colA = o;   o = align_up(o + B * NA * 16);
   L.geoB = o;   o = align_up(o + B * NB * 16);
   L.colB = o;   o = align_up(o + B * NB * 16);
-  L.hist = o;   o = align_up(o + B * size_t(256) * g.ntiles * 4);
-  L.dtot = o;   o = align_up(o + B * size_t(256) * 4);
+  L.hist = o;   o = align_up(o + B * size_t(kMaxDigits) * g.ntiles * 4);
+  L.dtot = o;   o = align_up(o + B * size_t(kMaxDigits) * 4);
   L.rpart = o;  o = align_up(o + B * size_t(g.units256) * 4 + 4);
   // forward work order: 64 counters (list sizes), then kPlanBuckets lists of
   // up to 2 * B * fwd_units work items
@@ -228,8 +230,8 @@ struct ImageView {
   int* kA; int* vA; int* kB; int* vB;   // radix ping-pong buffers: keys, point indices
   float4* geoA; float4* colA;           // and narrow point records (as geo, col)
   float4* geoB; float4* colB;
-  int* hist;                // [256 * ntiles] per (digit, tile) counts, then offsets
-  int* dtot;                // [256] per-digit totals of the current radix pass
+  int* hist;                // [kMaxDigits * ntiles] per (digit, tile) counts, then offsets
+  int* dtot;                // [kMaxDigits] per-digit totals of the current radix pass
   float* rpart;             // [units256] partial maxima of radius*sigma
   float* prec;              // [H, W, CP] backward pixel records
   float* gpart;             // [units256, 2] partial sums of dL/dsigma (shared sigma)
@@ -275,8 +277,8 @@ __host__ __device__ inline ImageView image_of(const ImageView& v0, int b) {
   v.colA = shift(v0.colA, bb * N);
   v.geoB = shift(v0.geoB, bb * N);
   v.colB = shift(v0.colB, bb * N);
-  v.hist = shift(v0.hist, bb * 256 * size_t(v0.ntiles));
-  v.dtot = shift(v0.dtot, bb * 256);
+  v.hist = shift(v0.hist, bb * kMaxDigits * size_t(v0.ntiles));
+  v.dtot = shift(v0.dtot, bb * kMaxDigits);
   v.rpart = shift(v0.rpart, bb * v0.units256);
   v.prec = shift(v0.prec, bb * HW * v0.CP);
   v.gpart = shift(v0.gpart, bb * v0.units256 * 2);

@@ -195,7 +195,7 @@ __device__ inline float4 point_values4(const ImageView& v, int j, int c) {
 
 // unit = one radix tile of kRadixTile points: bin key of every point, the
 // tile's maximum of radius*sigma and -- the first radix pass needs it -- the
-// tile's histogram of the lowest key digit.  lh: 256 ints of LDS.  With a
+// tile's histogram of the lowest key digit.  lh: kMaxDigits ints of LDS.  With a
 // single bin (no radix pass) the point order is already sorted and the
 // sorted records are written here.
 template <int ST = INTERP_STORAGE_F32>
@@ -211,7 +211,7 @@ __device__ inline void bin_keys(const ImageView& v, int tile, float* red4, int* 
     p[r] = v.pos[jc];
     sg[r] = sigma2_of(v, jc);
   }
-  lh[t] = 0;
+  for (int d = t; d < kMaxDigits; d += 256) lh[d] = 0;
   __syncthreads();
   float rmax = 0.0f;
 #pragma unroll
@@ -239,7 +239,8 @@ __device__ inline void bin_keys(const ImageView& v, int tile, float* red4, int* 
     }
   }
   __syncthreads();
-  if (v.npass > 0 && t <= mask0) v.hist[t * v.ntiles + tile] = lh[t];
+  if (v.npass > 0)
+    for (int d = t; d <= mask0; d += 256) v.hist[d * v.ntiles + tile] = lh[d];
   const float m = block_max(rmax, red4);
   if (t == 0) v.rpart[tile] = m;
 }
@@ -317,9 +318,33 @@ __device__ inline void radix_scan_digit(const ImageView& v, int p, int d, int* t
   if (threadIdx.x == 0) v.dtot[d] = carry;
 }
 
-// LDS ints radix_scatter needs: wrun[4][256], base[256], tstart[256], tmp4,
-// and the tile's keys and source slots in digit order.
-__host__ __device__ constexpr int radix_scatter_lds_ints() { return 6 * 256 + 4 + 2 * kRadixTile; }
+// The same for four digits per 256-thread block, one wavefront per digit,
+// when a pass has at most 64 tiles (a block per digit would spend its time
+// being dispatched).  unit = a group of four digits.
+__device__ inline void radix_scan_digits_small(const ImageView& v, int p, int unit) {
+  int shift, width;
+  radix_pass_bits(v, p, &shift, &width);
+  const int lane = threadIdx.x & 63;
+  const int d = unit * 4 + (int)(threadIdx.x >> 6);
+  if (d >= (1 << width)) return;
+  int* row = v.hist + (size_t)d * v.ntiles;
+  const int x = lane < v.ntiles ? row[lane] : 0;
+  int incl = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(incl, o);
+    if (lane >= o) incl += y;
+  }
+  if (lane < v.ntiles) row[lane] = incl - x;
+  if (lane == 63) v.dtot[d] = incl;
+}
+
+// LDS ints radix_scatter<kDig> needs: wrun[4][kDig], base[kDig], tstart[kDig],
+// tmp4, and the tile's keys and source slots in digit order.  kDig: the
+// digits a pass may have (256, or kMaxDigits for the single-call path's one
+// pass over keys of 9 or 10 bits).
+template <int kDig = 256>
+__host__ __device__ constexpr int radix_scatter_lds_ints() { return 6 * kDig + 4 + 2 * kRadixTile; }
 
 // unit = one tile: stable scatter of the tile's (key, point index) pairs by
 // the pass's digit.  Each wavefront ranks the kRadixTile / 4 consecutive keys
@@ -331,13 +356,15 @@ __host__ __device__ constexpr int radix_scatter_lds_ints() { return 6 * 256 + 4 
 // output.  The last pass writes the sorted keys, the permutation and the
 // sorted point records (x, y, k, R2 and the values padded to CS).
 // kWide: the records carry more than four values (CS > 4).
-template <bool kWide = false, int ST = INTERP_STORAGE_F32>
+template <bool kWide = false, int ST = INTERP_STORAGE_F32, int kDig = 256>
 __device__ inline void radix_scatter(const ImageView& v, int p, int tile, int* lds) {
-  int* wrun = lds;                 // [4][256]
-  int* base = lds + 1024;          // [256]
-  int* tstart = lds + 1280;        // [256]
-  int* tmp4 = lds + 1536;          // [4]
-  int* skey = lds + 1540;          // [kRadixTile]
+  static_assert(kDig % 256 == 0 && kDig <= kMaxDigits, "digits per thread");
+  constexpr int DPT = kDig / 256;  // digits per thread (thread t owns [t DPT, t DPT + DPT))
+  int* wrun = lds;                 // [4][kDig]
+  int* base = lds + 4 * kDig;      // [kDig]
+  int* tstart = base + kDig;       // [kDig]
+  int* tmp4 = tstart + kDig;       // [4]
+  int* skey = tmp4 + 4;            // [kRadixTile]
   int* ssrc = skey + kRadixTile;   // [kRadixTile] slot of the entry in the tile's input
   int shift, width;
   radix_pass_bits(v, p, &shift, &width);
@@ -358,15 +385,29 @@ __device__ inline void radix_scatter(const ImageView& v, int p, int tile, int* l
   const int s0 = wid * (kRadixTile / 4) + lane;  // this lane's first slot in the tile
 #pragma unroll
   for (int r = 0; r < kRadixItems; ++r) key[r] = kin[min(t0 + s0 + r * 64, v.N - 1)];
-  const int dt = t < ndig ? v.dtot[t] : 0;
-  const int th = t < ndig ? v.hist[t * v.ntiles + tile] : 0;
   // global start of each digit for this tile: digit base + tile offset
-  base[t] = block_exclusive_scan256(dt, tmp4) + th;
-  wrun[t] = 0; wrun[256 + t] = 0; wrun[512 + t] = 0; wrun[768 + t] = 0;
+  {
+    int dt[DPT], th[DPT], sum = 0;
+#pragma unroll
+    for (int i = 0; i < DPT; ++i) {
+      const int d = t * DPT + i;
+      dt[i] = d < ndig ? v.dtot[d] : 0;
+      th[i] = d < ndig ? v.hist[d * v.ntiles + tile] : 0;
+      sum += dt[i];
+    }
+    int pre = block_exclusive_scan256(sum, tmp4);
+#pragma unroll
+    for (int i = 0; i < DPT; ++i) {
+      base[t * DPT + i] = pre + th[i];
+      pre += dt[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 4 * DPT; ++i) wrun[i * 256 + t] = 0;
+  }
   __syncthreads();
   // 1) rank of every key among the equal digits of its wavefront's keys
   const unsigned long long below = (1ull << lane) - 1ull;
-  int* myrun = wrun + wid * 256;
+  int* myrun = wrun + wid * kDig;
 #pragma unroll
   for (int r = 0; r < kRadixItems; ++r) {
     const bool valid = s0 + r * 64 < tn;
@@ -386,16 +427,29 @@ __device__ inline void radix_scatter(const ImageView& v, int p, int tile, int* l
   }
   __syncthreads();
   // 2) per digit: start of each wavefront's keys and of the digit in the tile
-  int tot = 0;
-  if (t < ndig) {
-    const int c0 = wrun[t], c1 = wrun[256 + t], c2 = wrun[512 + t], c3 = wrun[768 + t];
-    wrun[t] = 0;
-    wrun[256 + t] = c0;
-    wrun[512 + t] = c0 + c1;
-    wrun[768 + t] = c0 + c1 + c2;
-    tot = c0 + c1 + c2 + c3;
+  {
+    int tot[DPT], sum = 0;
+#pragma unroll
+    for (int i = 0; i < DPT; ++i) {
+      const int d = t * DPT + i;
+      tot[i] = 0;
+      if (d < ndig) {
+        const int c0 = wrun[d], c1 = wrun[kDig + d], c2 = wrun[2 * kDig + d], c3 = wrun[3 * kDig + d];
+        wrun[d] = 0;
+        wrun[kDig + d] = c0;
+        wrun[2 * kDig + d] = c0 + c1;
+        wrun[3 * kDig + d] = c0 + c1 + c2;
+        tot[i] = c0 + c1 + c2 + c3;
+      }
+      sum += tot[i];
+    }
+    int pre = block_exclusive_scan256(sum, tmp4);
+#pragma unroll
+    for (int i = 0; i < DPT; ++i) {
+      tstart[t * DPT + i] = pre;
+      pre += tot[i];
+    }
   }
-  tstart[t] = block_exclusive_scan256(tot, tmp4);
   __syncthreads();
   // 3) the tile in digit order in LDS: key and input slot
 #pragma unroll

@@ -66,9 +66,10 @@ struct JobTable {
 // LDS of each phase kernel: only what its phase uses
 template <int PH>
 struct PhaseLds {
-  static constexpr int ints = (PH >= PH_SCAT0 && PH <= PH_SCAT2) ? dev::radix_scatter_lds_ints()
+  static constexpr int ints = (PH >= PH_SCAT0 && PH <= PH_SCAT2) ? dev::radix_scatter_lds_ints<256>()
                               : (PH == PH_BPOINT)                 ? 256 + 64
-                              : (PH >= PH_HIST0 && PH <= PH_HIST2) || PH == PH_KEYS ? 256
+                              : PH == PH_KEYS                     ? kMaxDigits
+                              : (PH >= PH_HIST0 && PH <= PH_HIST2) ? 256
                                                                   : 4;
   static constexpr int f4 = PH == PH_FWD ? dev::fwd_quarter_lds_f4<4>()
                             : PH == PH_BPOINT ? dev::kBwdStageF4

@@ -19,7 +19,7 @@ __device__ inline int xcd_tile(int per8) { return (blockIdx.x & 7) * per8 + (blo
 template <int ST>
 __global__ __launch_bounds__(256) void k_bin_keys(ImageView v0, int per8) {
   __shared__ float red4[4];
-  __shared__ int lh[256];
+  __shared__ int lh[kMaxDigits];
   const int tile = xcd_tile(per8);
   if (tile >= v0.ntiles) return;
   dev::bin_keys<ST>(image_of(v0, blockIdx.y), tile, red4, lh);
@@ -37,12 +37,16 @@ __global__ __launch_bounds__(256) void k_radix_scan(ImageView v0, int p) {
   dev::radix_scan_digit(image_of(v0, blockIdx.y), p, blockIdx.x, tmp4);
 }
 
-template <bool kWide, int ST>
+__global__ __launch_bounds__(256) void k_radix_scan_small(ImageView v0, int p) {
+  dev::radix_scan_digits_small(image_of(v0, blockIdx.y), p, blockIdx.x);
+}
+
+template <bool kWide, int ST, int kDig>
 __global__ __launch_bounds__(256) void k_radix_scatter(ImageView v0, int p, int per8) {
-  __shared__ int lds[dev::radix_scatter_lds_ints()];
+  __shared__ int lds[dev::radix_scatter_lds_ints<kDig>()];
   const int tile = xcd_tile(per8);
   if (tile >= v0.ntiles) return;
-  dev::radix_scatter<kWide, ST>(image_of(v0, blockIdx.y), p, tile, lds);
+  dev::radix_scatter<kWide, ST, kDig>(image_of(v0, blockIdx.y), p, tile, lds);
 }
 
 template <int ST>
@@ -273,7 +277,19 @@ hipError_t launch_backward_kv(const Geometry& g, const ImageView& v0, hipStream_
 
 // Binning (a1-a5) for values stored as ST.
 template <int ST>
-hipError_t launch_binning(const Geometry& g, const ImageView& v0, int* fplan, hipStream_t st) {
+hipError_t launch_binning(const Geometry& g0, const ImageView& v00, int* fplan, hipStream_t st) {
+  // Keys of 9 or 10 bits take one radix pass over up to kMaxDigits digits
+  // here instead of two of at most 256 (the serving path keeps the latter):
+  // the same stable order, one histogram, scan and scatter fewer.
+  Geometry g = g0;
+  ImageView v0 = v00;
+  if (g.kbits > 8 && g.kbits <= 10) {
+    g.npass = 1;
+    g.dbits = g.kbits;
+    v0.npass = 1;
+    v0.dbits = g.kbits;
+  }
+  const bool wide_digits = g.npass == 1 && g.dbits > 8;
   const int per8 = (g.ntiles + 7) / 8;  // radix tiles per XCD
   if (g.N > 0) {
     ProfRange pr_("bin_keys", st);
@@ -287,16 +303,28 @@ hipError_t launch_binning(const Geometry& g, const ImageView& v0, int* fplan, hi
     {
       ProfRange pr_("radix_scan", st);
       const int width = std::min(g.dbits, g.kbits - p * g.dbits);
-      hipLaunchKernelGGL(k_radix_scan, dim3(1u << width, g.B), dim3(256), 0, st, v0, p);
+      if (g.ntiles <= 64)
+        hipLaunchKernelGGL(k_radix_scan_small, dim3(((1u << width) + 3) / 4, g.B), dim3(256), 0, st,
+                           v0, p);
+      else
+        hipLaunchKernelGGL(k_radix_scan, dim3(1u << width, g.B), dim3(256), 0, st, v0, p);
     }
     {
       ProfRange pr_("radix_scatter", st);
-      if (g.CS > 4)
-        hipLaunchKernelGGL((k_radix_scatter<true, ST>), dim3(8 * per8, g.B), dim3(256), 0, st, v0,
-                           p, per8);
-      else
-        hipLaunchKernelGGL((k_radix_scatter<false, ST>), dim3(8 * per8, g.B), dim3(256), 0, st,
+      if (wide_digits) {
+        if (g.CS > 4)
+          hipLaunchKernelGGL((k_radix_scatter<true, ST, kMaxDigits>), dim3(8 * per8, g.B), dim3(256),
+                             0, st, v0, p, per8);
+        else
+          hipLaunchKernelGGL((k_radix_scatter<false, ST, kMaxDigits>), dim3(8 * per8, g.B),
+                             dim3(256), 0, st, v0, p, per8);
+      } else if (g.CS > 4) {
+        hipLaunchKernelGGL((k_radix_scatter<true, ST, 256>), dim3(8 * per8, g.B), dim3(256), 0, st,
                            v0, p, per8);
+      } else {
+        hipLaunchKernelGGL((k_radix_scatter<false, ST, 256>), dim3(8 * per8, g.B), dim3(256), 0,
+                           st, v0, p, per8);
+      }
     }
   }
   if (g.CS > 4 && g.npass > 0 && g.N > 0) {
