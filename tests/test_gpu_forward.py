@@ -38,6 +38,15 @@ def test_bins_tiles_ragged(tile):
                                       blob_std=(2.0, 6.0)), tile)
 
 
+@pytest.mark.parametrize("H,W,N", [(160, 200, 20000), (256, 256, 70000), (120, 72, 900)])
+def test_bins_single_pass_nine_and_ten_bit_keys(H, W, N):
+    """500 and 1024 bins (keys of 9 and 10 bits: one radix pass of up to 1024
+    digits, scan by one wavefront per digit), and 135 bins with fewer points
+    than one radix tile."""
+    _check_bins(synth.random_workload(H + W + N, 2, N, H, W, C=3, sigma=(0.5, 2.0), blob_frac=0.5,
+                                      blob_std=(4.0, 12.0)))
+
+
 def test_bins_edges_borders_outside_and_one_big_bin():
     rng = np.random.default_rng(7)
     H, W = 40, 50
