@@ -90,8 +90,8 @@ enum { INTERP_STORAGE_F32 = 0, INTERP_STORAGE_BF16 = 1, INTERP_STORAGE_F16 = 2 }
  *          points: 4, 8, 16, 32 or 64; 0 selects the default 8
  *   sigma_per_point  1: sigma is [B, N]; 0: one shared sigma per image, [B]
  *          (with INTERP_KERNEL_DIAGONAL: [B, N, 2] and [B, 2])
- *   kernel 0 or INTERP_KERNEL_* flags (above); C is at most 31 with
- *          INTERP_KERNEL_NORMALIZED.  The serving path takes kernel 0 only.
+ *   kernel 0 or INTERP_KERNEL_* flags (above).  The serving path takes
+ *          kernel 0 only.
  *   storage INTERP_STORAGE_* (above); the serving path takes float32 only.
  */
 typedef struct interp_problem {

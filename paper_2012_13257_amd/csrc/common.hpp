@@ -154,8 +154,6 @@ inline std::string make_geometry(const interp_problem* p, Geometry* g) {
   if (p->sigma_per_point != 0 && p->sigma_per_point != 1) return "sigma_per_point must be 0 or 1";
   if (p->kernel < 0 || p->kernel > (INTERP_KERNEL_NORMALIZED | INTERP_KERNEL_DIAGONAL))
     return "kernel must be a combination of INTERP_KERNEL_NORMALIZED and INTERP_KERNEL_DIAGONAL";
-  const int norm = (p->kernel & INTERP_KERNEL_NORMALIZED) ? 1 : 0;
-  if (p->C + norm > kMaxChannels) return "C must be at most 31 with a normalised kernel";
   if (p->storage < INTERP_STORAGE_F32 || p->storage > INTERP_STORAGE_F16)
     return "storage must be INTERP_STORAGE_F32, _BF16 or _F16";
   if (p->storage != INTERP_STORAGE_F32 && p->kernel != 0)
@@ -166,17 +164,16 @@ inline std::string make_geometry(const interp_problem* p, Geometry* g) {
   const long long BHW = (long long)p->B * p->H * p->W;
   if (BN >= (1LL << 31)) return "B*N must be below 2^31";
   if (BHW >= (1LL << 31)) return "B*H*W must be below 2^31";
-  if (BN * channel_template(p->C + norm) >= (1LL << 31)) return "B*N*C must be below 2^31";
-  if (BHW * pix_stride(p->C + norm) >= (1LL << 31)) return "B*H*W*(C+1) must be below 2^31";
+  if (BN * channel_template(p->C) >= (1LL << 31)) return "B*N*C must be below 2^31";
+  if (BHW * pix_stride(p->C) >= (1LL << 31)) return "B*H*W*(C+1) must be below 2^31";
   g->B = p->B; g->N = p->N; g->C = p->C; g->H = p->H; g->W = p->W; g->T = T;
   g->nbx = (p->W + T - 1) / T;
   g->nby = (p->H + T - 1) / T;
   g->nb = g->nbx * g->nby;
-  g->CT = channel_template(p->C + norm);
-  g->CS = col_stride(p->C + norm);
-  // pixel records hold a gradient slot per channel (not for the density
-  // factor's slot) and beta
-  g->CP = (g->CT - norm + 1 + 3) / 4 * 4;
+  g->CT = channel_template(p->C);
+  g->CS = col_stride(p->C);
+  // pixel records: a gradient slot per channel, then beta
+  g->CP = (g->CT + 1 + 3) / 4 * 4;
   g->radius = p->radius;
   g->per_point = p->sigma_per_point;
   g->kern = p->kernel;
@@ -201,7 +198,6 @@ struct ImageView {
   int kern, nsig;           // kernel flags; sigma values per point (1 or 2)
   int st;                   // INTERP_STORAGE_* of values, out, grad_out, grad_values, col
   int values_vec4;          // C % 4 == 0 and values aligned to four elements: vector loads
-  int zslot;                // normalised: record slot of the density factor, else -1
   float r2;                 // f32(radius * radius): the diagonal kernel's test
   int npass, dbits, kbits, ntiles, units256;
   int bx_blocks, by_blocks;
@@ -297,7 +293,6 @@ inline ImageView make_view(const Geometry& g, const Layout& L, void* saved, void
   v.CS = g.CS; v.CP = g.CP; v.per_point = g.per_point;
   v.kern = g.kern; v.nsig = g.nsig; v.st = g.st;
   v.values_vec4 = g.C % 4 == 0 && reinterpret_cast<uintptr_t>(values) % (4 * g.vbytes) == 0;
-  v.zslot = (g.kern & INTERP_KERNEL_NORMALIZED) ? g.CT - 1 : -1;
   v.r2 = g.radius * g.radius;  // one rounded float multiply, as the test specifies
   v.npass = g.npass; v.dbits = g.dbits; v.kbits = g.kbits; v.ntiles = g.ntiles;
   v.units256 = g.units256;

@@ -68,9 +68,15 @@ __device__ inline float4 make_geo(float2 p, float2 sg, float radius, bool diag) 
   return make_float4(p.x, p.y, kk, R2);
 }
 
-// The normal density's factor 1/(2 pi sigma_x sigma_y) of a normalised kernel.
-__device__ inline float density_factor(float2 sg) {
-  return 1.0f / (6.28318530717958648f * sg.x * sg.y);
+// The normal density's factor 1/(2 pi sigma_x sigma_y) of a normalised
+// kernel, from the point's record: the isotropic record holds
+// k = -log2(e) / (2 sigma^2), so the factor is k * (-1 / (pi log2(e)));
+// the diagonal record holds 1/sigma_x and 1/sigma_y.  (A few float32
+// roundings from the exact factor: far inside the outputs' tolerance.)
+template <bool kDiag>
+__device__ inline float record_density(float4 g) {
+  if constexpr (kDiag) return (g.z * g.w) * 0.159154943091895336f;  // 1 / (2 pi)
+  else return g.z * -0.220635600152651643f;                        // -1 / (pi log2(e))
 }
 
 // Truncation radius (pixels) of a point along its longer axis.
@@ -169,8 +175,7 @@ template <> struct Val<INTERP_STORAGE_F16> {
 // Binning: stable LSD radix sort of the bin keys (no global atomics)
 // ---------------------------------------------------------------------------
 
-// The record of point j: geo (make_geo) and its values padded to CS; a
-// normalised kernel's records carry the density factor in slot zslot.
+// The record of point j: geo (make_geo) and its values padded to CS.
 __device__ inline float4 point_geo(const ImageView& v, int j) {
   return make_geo(v.pos[j], sigma2_of(v, j), v.radius, v.nsig == 2);
 }
@@ -184,11 +189,6 @@ __device__ inline float4 point_values4(const ImageView& v, int j, int c) {
   } else {
 #pragma unroll
     for (int i = 0; i < 4; ++i) q[i] = c + i < v.C ? Val<ST>::load(v.values, base + c + i) : 0.0f;
-  }
-  if (v.zslot >= c && v.zslot < c + 4) {
-    const float z = density_factor(sigma2_of(v, j));
-#pragma unroll
-    for (int i = 0; i < 4; ++i) q[i] = c + i == v.zslot ? z : q[i];
   }
   return make_float4(q[0], q[1], q[2], q[3]);
 }
@@ -639,7 +639,7 @@ template <int CT, int KV = 0, int ST = INTERP_STORAGE_F32>
 __device__ inline void forward_tile(const ImageView& v, int tile, float4* s_geo /*[4][64]*/,
                                     float4* s_col /*[4][64*CS/4]*/) {
   constexpr int CS = CT < 4 ? 4 : CT;
-  constexpr int NC = kNormalized<KV> ? CT - 1 : CT;  // channel slots (the last is the factor)
+  constexpr int NC = CT;
   const float r2 = v.r2;
   const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wgx = fwd_tiles_x(v.bx_blocks);
@@ -704,7 +704,7 @@ __device__ inline void forward_tile(const ImageView& v, int tile, float4* s_geo 
           cc[4 * q] = tq.x; cc[4 * q + 1] = tq.y; cc[4 * q + 2] = tq.z; cc[4 * q + 3] = tq.w;
         }
         float w = pair_weight<KV>(fu, fv, r, r2);
-        if constexpr (kNormalized<KV>) w *= cc[CT - 1];
+        if constexpr (kNormalized<KV>) w *= record_density<kDiagonal<KV>>(r);
         Z += w;
 #pragma unroll
         for (int k = 0; k < NC; ++k) acc[k] = __builtin_fmaf(w, cc[k], acc[k]);
@@ -809,7 +809,7 @@ __device__ inline bool unit_is_heavy(const int cost[4]) {
 template <int CT, int KV = 0, int ST = INTERP_STORAGE_F32>
 __device__ inline void forward_block_q(const ImageView& v, int unit, int mode, float4* s_rec) {
   static_assert(CT <= 4, "the quarter lists hold the values of a record in one float4");
-  constexpr int NC = kNormalized<KV> ? CT - 1 : CT;  // channel slots (the last is the factor)
+  constexpr int NC = CT;
   const float r2 = v.r2;
   const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int grp = lane >> 4, p = lane & 15;
@@ -951,7 +951,7 @@ __device__ inline void forward_block_q(const ImageView& v, int unit, int mode, f
 #pragma unroll
           for (int k = 0; k < CT; ++k) cc[k] = LV[4 * CT * i + k];
           float w = pair_weight<KV>(fu, fv, r, r2);
-          if constexpr (kNormalized<KV>) w *= cc[CT - 1];
+          if constexpr (kNormalized<KV>) w *= record_density<kDiagonal<KV>>(r);
           Z[q] += w;
 #pragma unroll
           for (int k = 0; k < NC; ++k) acc[q][k] = __builtin_fmaf(w, cc[k], acc[q][k]);
@@ -1071,7 +1071,7 @@ __device__ inline void bwd_point(const ImageView& v, int unit, float* red4, int*
                                  float4* stage) {
   constexpr int CS = CT < 4 ? 4 : CT;
   constexpr bool kD = kDiagonal<KV>, kN = kNormalized<KV>;
-  constexpr int NC = kN ? CT - 1 : CT;  // channel slots (the last is the density factor)
+  constexpr int NC = CT;
   constexpr int CP = (NC + 1 + 3) / 4 * 4;  // pixel record: G'_0..G'_{NC-1}, beta
   constexpr int CP4 = CP / 4;
   int* order = lds;            // [256] local point index by regrouped slot
@@ -1136,7 +1136,7 @@ __device__ inline void bwd_point(const ImageView& v, int unit, float* red4, int*
     float cc[CT];
 #pragma unroll
     for (int k = 0; k < CT; ++k) cc[k] = Val<ST>::load(v.col, (size_t)t * CS + k);
-    const float zeta = kN ? cc[CT - 1] : 1.0f;
+    const float zeta = kN ? record_density<kD>(g) : 1.0f;
     const int j = v.perm[t];
     const float2 sg = sigma2_of(v, j);
     const float Rhx = conservative_reach(__fmul_rn(v.radius, sg.x));
@@ -1338,7 +1338,7 @@ __device__ inline void bwd_point_wide(const ImageView& v, int unit, float* red4,
   static_assert(CT >= 8, "eight lanes per point pay off for wide records only");
   constexpr int CS = CT;
   constexpr bool kD = kDiagonal<KV>, kN = kNormalized<KV>;
-  constexpr int NC = kN ? CT - 1 : CT;
+  constexpr int NC = CT;
   constexpr int CP = (NC + 1 + 3) / 4 * 4;
   constexpr int CP4 = CP / 4;
   const int base = unit * 256;
@@ -1379,7 +1379,7 @@ __device__ inline void bwd_point_wide(const ImageView& v, int unit, float* red4,
       const float4 c4 = Val<ST>::load4(v.col, (size_t)t * (CS / 4) + q);
       cc[4 * q] = c4.x; cc[4 * q + 1] = c4.y; cc[4 * q + 2] = c4.z; cc[4 * q + 3] = c4.w;
     }
-    const float zeta = kN ? cc[CT - 1] : 1.0f;
+    const float zeta = kN ? record_density<kD>(g) : 1.0f;
     const int j = v.perm[t];
     const float2 sg = sigma2_of(v, j);
     const float Rh = conservative_reach(__fmul_rn(v.radius, sg.y));  // along y

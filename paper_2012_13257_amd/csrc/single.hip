@@ -222,8 +222,7 @@ hipError_t launch_backward_t(const Geometry& g, const ImageView& v0, hipStream_t
     ProfRange pr_("bwd_pixel", st);
     // gradient slots of the pixel record: the density factor's slot has none
     // (planar records for the eight-lanes-per-point adjoint of CT >= 8)
-    constexpr int NP = (KV & INTERP_KERNEL_NORMALIZED) ? CT - 1 : CT;
-    hipLaunchKernelGGL((k_bwd_pixel<NP, ST, (CT >= 8)>), dim3(cdiv((long long)g.H * g.W, 256), g.B),
+    hipLaunchKernelGGL((k_bwd_pixel<CT, ST, (CT >= 8)>), dim3(cdiv((long long)g.H * g.W, 256), g.B),
                        dim3(256), 0, st, v0);
   }
   if (g.N > 0) {
@@ -243,13 +242,11 @@ hipError_t launch_backward_t(const Geometry& g, const ImageView& v0, hipStream_t
   return hipSuccess;
 }
 
-// Channel-count dispatch of one kernel variant (a normalised kernel's
-// records hold the density factor in an extra slot, so its CT is at least 2).
+// Channel-count dispatch of one kernel variant.
 template <int KV, int ST>
 hipError_t launch_forward_kv(const Geometry& g, const ImageView& v0, int* fplan, hipStream_t st) {
-  constexpr bool kN = (KV & INTERP_KERNEL_NORMALIZED) != 0;
   switch (g.CT) {
-    case 1: if constexpr (!kN) return launch_forward_t<1, KV, ST>(g, v0, fplan, st); break;
+    case 1: return launch_forward_t<1, KV, ST>(g, v0, fplan, st);
     case 2: return launch_forward_t<2, KV, ST>(g, v0, fplan, st);
     case 3: return launch_forward_t<3, KV, ST>(g, v0, fplan, st);
     case 4: return launch_forward_t<4, KV, ST>(g, v0, fplan, st);
@@ -262,9 +259,8 @@ hipError_t launch_forward_kv(const Geometry& g, const ImageView& v0, int* fplan,
 
 template <int KV, int ST>
 hipError_t launch_backward_kv(const Geometry& g, const ImageView& v0, hipStream_t st) {
-  constexpr bool kN = (KV & INTERP_KERNEL_NORMALIZED) != 0;
   switch (g.CT) {
-    case 1: if constexpr (!kN) return launch_backward_t<1, KV, ST>(g, v0, st); break;
+    case 1: return launch_backward_t<1, KV, ST>(g, v0, st);
     case 2: return launch_backward_t<2, KV, ST>(g, v0, st);
     case 3: return launch_backward_t<3, KV, ST>(g, v0, st);
     case 4: return launch_backward_t<4, KV, ST>(g, v0, st);

@@ -53,13 +53,22 @@ def test_sizes_valid_and_invalid(L):
     bad = [dict(C=0), dict(C=33), dict(radius=0.0), dict(radius=float("nan")), dict(radius=12.5),
            dict(tile=3), dict(tile=128), dict(H=0), dict(W=40000), dict(B=0), dict(N=-1),
            dict(sigma_per_point=2), dict(B=2, N=1 << 30), dict(kernel=4), dict(kernel=-1),
-           dict(kernel=1, C=32)]
+           dict(kernel=1, C=33)]
     for kw in bad:
         q = _prob(**kw)
         assert L.interp_workspace_bytes(ctypes.byref(q)) == 0, kw
         assert L.interp_saved_bytes(ctypes.byref(q)) == 0, kw
         assert L.interp_last_error().decode(), kw
     assert L.interp_saved_bytes(None) == 0
+
+
+def test_normalised_kernel_takes_the_default_records(L):
+    """The normalised kernel derives the density factor from the position
+    record: same saved state and workspace as the default kernel, C = 32 valid."""
+    for C in (3, 4, 32):
+        a, b = _prob(C=C), _prob(C=C, kernel=1)
+        assert L.interp_saved_bytes(ctypes.byref(a)) == L.interp_saved_bytes(ctypes.byref(b)) > 0
+        assert L.interp_workspace_bytes(ctypes.byref(a)) == L.interp_workspace_bytes(ctypes.byref(b))
 
 
 def test_tile_zero_means_default(L):
