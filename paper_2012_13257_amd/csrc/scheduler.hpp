@@ -130,6 +130,16 @@ class Scheduler {
     queue_.push_back(j.get());
     jobs_[j->ticket] = std::move(j);
     ++outstanding_;
+    // When nothing runs or waits, the request is admitted and launched from
+    // the caller's thread at once: waking the scheduler thread first would
+    // cost a small request a noticeable part of its latency.  (The thread
+    // is still notified: it polls the batch to completion.)
+    if (!in_round_ && queue_.size() == 1 && pending_.empty() && !any_busy()) {
+      in_round_ = true;
+      round(lk);
+      in_round_ = false;
+      if (outstanding_ == 0) done_cv_.notify_all();
+    }
     lk.unlock();
     cv_.notify_all();
     return INTERP_OK;
@@ -178,6 +188,12 @@ class Scheduler {
   int peak_concurrent_batches() const { return peak_ctx_; }
 
  private:
+  bool any_busy() const {
+    for (bool b : ctx_busy_)
+      if (b) return true;
+    return false;
+  }
+
   void finish(J* j, int32_t state, int32_t err) {
     j->state = state;
     j->err = err;
@@ -193,9 +209,11 @@ class Scheduler {
   // One scheduling round; returns true if a batch is in flight.  Entered and
   // left with the lock held, which is released around every executor call
   // (event queries, table uploads, graph launches can take a while and must
-  // not hold up submit / poll).  Only this thread touches the contexts, the
-  // pending list and the arena; a job's request and arena range do not change
-  // while it runs, and poll never frees a running job.
+  // not hold up submit / poll).  One round runs at a time (in_round_, taken
+  // under the lock by the scheduler thread or by a submit that finds the
+  // scheduler idle): only the round touches the contexts, the pending list
+  // and the arena; a job's request and arena range do not change while it
+  // runs, and poll never frees a running job.
   bool round(std::unique_lock<std::mutex>& lk) {
     // 1. retire finished batches
     std::vector<int> busy, status;
@@ -267,7 +285,15 @@ class Scheduler {
     ex_->thread_init();
     std::unique_lock<std::mutex> lk(mu_);
     while (true) {
+      if (in_round_) {  // a submit runs a round on its own thread: let it finish
+        lk.unlock();
+        std::this_thread::yield();
+        lk.lock();
+        continue;
+      }
+      in_round_ = true;
       const bool busy = round(lk);
+      in_round_ = false;
       if (outstanding_ == 0) done_cv_.notify_all();
       if (stop_) break;
       if (busy) {
@@ -279,8 +305,9 @@ class Scheduler {
         std::this_thread::yield();
         lk.lock();
       } else {
-        cv_.wait_for(lk, std::chrono::milliseconds(2),
-                     [this] { return stop_ || !queue_.empty() || !pending_.empty(); });
+        cv_.wait_for(lk, std::chrono::milliseconds(2), [this] {
+          return stop_ || !queue_.empty() || !pending_.empty() || any_busy();
+        });
       }
     }
     // shutdown: fail what never started, finish what runs
@@ -317,6 +344,7 @@ class Scheduler {
   int slots_used_ = 0;
   int64_t outstanding_ = 0;
   bool stop_ = false;
+  bool in_round_ = false;
   uint64_t peak_arena_ = 0;
   int peak_slots_ = 0, batches_ = 0, peak_ctx_ = 0;
   std::thread thread_;

@@ -285,7 +285,20 @@ class GpuExecutor {
 
   void thread_init() { hipSetDevice(device_); }
 
+  // Also called on a submitting thread (an idle server launches at once):
+  // the server's device is made current for the call and the caller's
+  // restored afterwards.
   int launch(int c, std::vector<Job<Request>*>& jobs) {
+    int prev = device_;
+    if (hipGetDevice(&prev) != hipSuccess) prev = device_;
+    if (prev != device_) hipSetDevice(device_);
+    const int rc = launch_on_device(c, jobs);
+    if (prev != device_) hipSetDevice(prev);
+    return rc;
+  }
+
+ private:
+  int launch_on_device(int c, std::vector<Job<Request>*>& jobs) {
     Ctx& x = ctx_[c];
     JobTable* T = x.htab;
     const int nj = (int)jobs.size();
@@ -348,6 +361,7 @@ class GpuExecutor {
     return INTERP_OK;
   }
 
+ public:
   int query(int c) {
     const hipError_t e = hipEventQuery(ctx_[c].done);
     if (e == hipSuccess) return 1;

@@ -29,6 +29,10 @@ def _workload(seed, kern, per_point, B=2, N=300, H=23, W=37, C=3):
 @pytest.mark.parametrize("per_point", [True, False])
 @pytest.mark.parametrize("C", [1, 3, 6])
 def test_variant_forward_and_backward_match_oracle(kern, per_point, C):
+    _check_variant(kern, per_point, C)
+
+
+def _check_variant(kern, per_point, C):
     import torch
     from paper_2012_13257_amd import interp
     pos, sig, val, G, H, W = _workload(900 + 7 * C + 3 * KERNELS.index(kern) + per_point,
@@ -50,6 +54,14 @@ def test_variant_forward_and_backward_match_oracle(kern, per_point, C):
     check_grad(gp.cpu().numpy(), ref["grad_pos"], ref["scale_pos"], kern + " pos")
     check_grad(gv.cpu().numpy(), ref["grad_values"], ref["scale_values"], kern + " values")
     check_grad(gs.cpu().numpy(), ref["grad_sigma"], ref["scale_sigma"], kern + " sigma")
+
+
+@pytest.mark.parametrize("kern", ["iso_norm", "diag_norm"])
+@pytest.mark.parametrize("C", [4, 32])
+def test_normalised_four_and_thirty_two_channels(kern, C):
+    """The normalised kernel with C = 4 (the four-value records of the narrow
+    path) and C = 32 (the widest records) against the variant oracle."""
+    _check_variant(kern, True, C)
 
 
 @pytest.mark.parametrize("kern", ["iso_norm", "diag"])
