@@ -220,8 +220,7 @@ template <int CT, int KV, int ST>
 hipError_t launch_backward_t(const Geometry& g, const ImageView& v0, hipStream_t st) {
   {
     ProfRange pr_("bwd_pixel", st);
-    // gradient slots of the pixel record: the density factor's slot has none
-    // (planar records for the eight-lanes-per-point adjoint of CT >= 8)
+    // planar records for the eight-lanes-per-point adjoint of CT >= 8
     hipLaunchKernelGGL((k_bwd_pixel<CT, ST, (CT >= 8)>), dim3(cdiv((long long)g.H * g.W, 256), g.B),
                        dim3(256), 0, st, v0);
   }
