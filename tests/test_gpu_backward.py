@@ -42,6 +42,13 @@ def test_backward_per_point_sigma_multitile(C):
                                                values="normal", blob_frac=0.5, blob_std=(2.0, 5.0)))
 
 
+@pytest.mark.parametrize("C", [3, 8])
+def test_backward_single_radix_pass_nine_bit_keys(C):
+    """The backward after a one-pass sort of 9-bit keys (160 x 200 image)."""
+    _full_backward_check(synth.random_workload(320 + C, 1, 3000, 160, 200, C=C, sigma=(0.5, 2.0),
+                                               values="normal", blob_frac=0.5, blob_std=(4.0, 12.0)))
+
+
 @pytest.mark.parametrize("C", [3, 12])
 def test_backward_shared_sigma_batch(C):
     """Shared sigma: the per-unit partial sums of dL/dsigma and their

@@ -88,6 +88,14 @@ def test_forward_channels_ragged_multitile(C):
                                               values="normal", blob_frac=0.4, blob_std=(2.0, 5.0)))
 
 
+@pytest.mark.parametrize("C", [3, 8])
+def test_forward_single_radix_pass_nine_bit_keys(C):
+    """A 160 x 200 image (500 bins: one radix pass over 9-bit keys), narrow
+    records carried through the pass and wide records placed afterwards."""
+    _full_forward_check(synth.random_workload(300 + C, 1, 4000, 160, 200, C=C, sigma=(0.5, 2.0),
+                                              values="normal", blob_frac=0.5, blob_std=(4.0, 12.0)))
+
+
 @pytest.mark.parametrize("tile", [4, 16, 64])
 def test_forward_other_tiles_shared_sigma(tile):
     _full_forward_check(synth.random_workload(300 + tile, 1, 900, 40, 33, C=3, sigma=1.3), tile)
