@@ -104,6 +104,10 @@ struct Layout {
       fwd_work_bytes, work_bytes;
 };
 
+// Digits a radix pass of this geometry may have: 2^kbits for keys of up to
+// 10 bits (one pass on the single-call path), else 256.
+inline int max_digits(const Geometry& g) { return g.kbits <= 10 ? 1 << g.kbits : 256; }
+
 inline Layout make_layout(const Geometry& g) {
   Layout L{};
   size_t o = 0;
@@ -129,8 +133,8 @@ inline Layout make_layout(const Geometry& g) {
   L.colA = o;   o = align_up(o + B * NA * 16);
   L.geoB = o;   o = align_up(o + B * NB * 16);
   L.colB = o;   o = align_up(o + B * NB * 16);
-  L.hist = o;   o = align_up(o + B * size_t(kMaxDigits) * g.ntiles * 4);
-  L.dtot = o;   o = align_up(o + B * size_t(kMaxDigits) * 4);
+  L.hist = o;   o = align_up(o + B * size_t(max_digits(g)) * g.ntiles * 4);
+  L.dtot = o;   o = align_up(o + B * size_t(max_digits(g)) * 4);
   L.rpart = o;  o = align_up(o + B * size_t(g.units256) * 4 + 4);
   // forward work order: 64 counters (list sizes), then kPlanBuckets lists of
   // up to 2 * B * fwd_units work items
@@ -226,8 +230,9 @@ struct ImageView {
   int* kA; int* vA; int* kB; int* vB;   // radix ping-pong buffers: keys, point indices
   float4* geoA; float4* colA;           // and narrow point records (as geo, col)
   float4* geoB; float4* colB;
-  int* hist;                // [kMaxDigits * ntiles] per (digit, tile) counts, then offsets
-  int* dtot;                // [kMaxDigits] per-digit totals of the current radix pass
+  int* hist;                // [hdig * ntiles] per (digit, tile) counts, then offsets
+  int* dtot;                // [hdig] per-digit totals of the current radix pass
+  int hdig;                 // digits per pass the hist and dtot arrays hold (max_digits)
   float* rpart;             // [units256] partial maxima of radius*sigma
   float* prec;              // [H, W, CP] backward pixel records
   float* gpart;             // [units256, 2] partial sums of dL/dsigma (shared sigma)
@@ -273,8 +278,8 @@ __host__ __device__ inline ImageView image_of(const ImageView& v0, int b) {
   v.colA = shift(v0.colA, bb * N);
   v.geoB = shift(v0.geoB, bb * N);
   v.colB = shift(v0.colB, bb * N);
-  v.hist = shift(v0.hist, bb * kMaxDigits * size_t(v0.ntiles));
-  v.dtot = shift(v0.dtot, bb * kMaxDigits);
+  v.hist = shift(v0.hist, bb * size_t(v0.hdig) * v0.ntiles);
+  v.dtot = shift(v0.dtot, bb * size_t(v0.hdig));
   v.rpart = shift(v0.rpart, bb * v0.units256);
   v.prec = shift(v0.prec, bb * HW * v0.CP);
   v.gpart = shift(v0.gpart, bb * v0.units256 * 2);
@@ -295,6 +300,7 @@ inline ImageView make_view(const Geometry& g, const Layout& L, void* saved, void
   v.values_vec4 = g.C % 4 == 0 && reinterpret_cast<uintptr_t>(values) % (4 * g.vbytes) == 0;
   v.r2 = g.radius * g.radius;  // one rounded float multiply, as the test specifies
   v.npass = g.npass; v.dbits = g.dbits; v.kbits = g.kbits; v.ntiles = g.ntiles;
+  v.hdig = max_digits(g);
   v.units256 = g.units256;
   v.bx_blocks = g.bx_blocks; v.by_blocks = g.by_blocks;
   v.radius = g.radius;
