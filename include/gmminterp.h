@@ -267,6 +267,19 @@ int interp_server_create(const interp_server_config* cfg, interp_server** out);
  * success *ticket identifies the request. */
 int interp_submit(interp_server* s, const interp_request* req, uint64_t* ticket);
 
+/* Non-blocking submit of n requests in one call, queued in array order.
+ * Every request is checked first: EINVAL (naming the request's index) when
+ * one is invalid, and then none is queued.  Otherwise the requests are queued
+ * in order until one cannot be (ENOMEM: it can never fit the budget; EAGAIN:
+ * the queue is full), whose code is returned; *n_queued counts the requests
+ * queued (tickets[0 .. *n_queued) identify them; the rest are not queued and
+ * may be submitted again).  reqs: n requests as for interp_submit; tickets:
+ * room for n tickets (host memory, the caller's).  One call takes the
+ * server's lock once, so a client with many requests at hand does not pay a
+ * submit per request. */
+int interp_submit_many(interp_server* s, const interp_request* reqs, int32_t n, uint64_t* tickets,
+                       int32_t* n_queued);
+
 /* Non-blocking status query.  ENOTFOUND for an unknown ticket.  A ticket is
  * forgotten after a poll that returns DONE or FAILED. */
 int interp_poll(interp_server* s, uint64_t ticket, interp_status* status);

@@ -61,7 +61,7 @@ EXPORTS = [
     "interp_workspace_bytes", "interp_saved_bytes", "interp_forward", "interp_forward_noalloc",
     "interp_backward",
     "interp_debug_bins", "interp_last_error", "interp_profile_enable", "interp_profile_read",
-    "interp_server_create", "interp_submit",
+    "interp_server_create", "interp_submit", "interp_submit_many",
     "interp_poll", "interp_server_drain", "interp_server_destroy",
 ]
 
@@ -100,6 +100,9 @@ def _declare(L):
     L.interp_server_create.restype = ctypes.c_int
     L.interp_submit.argtypes = [c_void_p, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
     L.interp_submit.restype = ctypes.c_int
+    L.interp_submit_many.argtypes = [c_void_p, ctypes.POINTER(Request), c_int32,
+                                     ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(c_int32)]
+    L.interp_submit_many.restype = ctypes.c_int
     L.interp_poll.argtypes = [c_void_p, ctypes.c_uint64, ctypes.POINTER(Status)]
     L.interp_poll.restype = ctypes.c_int
     L.interp_server_drain.argtypes = [c_void_p, ctypes.c_int64]

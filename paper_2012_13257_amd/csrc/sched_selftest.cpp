@@ -113,6 +113,13 @@ int gmm_fake_submit(void* h, uint64_t bytes, int64_t delay_us, int fail, uint64_
   return static_cast<Harness*>(h)->sched.submit(FakeReq{delay_us, fail}, bytes, ticket);
 }
 
+// n requests of bytes[i] bytes in one call (delay_us and fail as above)
+int gmm_fake_submit_many(void* h, const uint64_t* bytes, int n, int64_t delay_us, int fail,
+                         uint64_t* tickets, int* accepted) {
+  std::vector<FakeReq> rq(n, FakeReq{delay_us, fail});
+  return static_cast<Harness*>(h)->sched.submit_many(rq.data(), bytes, n, tickets, accepted);
+}
+
 int gmm_fake_poll(void* h, uint64_t ticket, interp_status* st) {
   return static_cast<Harness*>(h)->sched.poll(ticket, st);
 }

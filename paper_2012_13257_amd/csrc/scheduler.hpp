@@ -15,6 +15,7 @@
 
 #include <time.h>
 
+#include <algorithm>
 #include <condition_variable>
 #include <cstdint>
 #include <deque>
@@ -117,24 +118,47 @@ class Scheduler {
   ~Scheduler() { shutdown(); }
 
   int submit(const Payload& p, uint64_t bytes, uint64_t* ticket) {
+    int accepted = 0;
+    return submit_many(&p, &bytes, 1, ticket, &accepted);
+  }
+
+  // Queues p[0..n) in order under one lock: the first request that cannot be
+  // queued (ENOMEM: it can never fit the budget; EAGAIN: the queue is full or
+  // the server stops) ends the call with its code, and *accepted (tickets[0..
+  // *accepted)) counts the ones queued before it.
+  int submit_many(const Payload* p, const uint64_t* bytes, int n, uint64_t* tickets,
+                  int* accepted) {
+    *accepted = 0;
+    // the jobs are built before the lock is taken, so that a large batch
+    // holds the scheduler thread up only while it is linked into the queue
+    std::vector<std::unique_ptr<J>> js(n);
+    for (int i = 0; i < n; ++i) {
+      js[i] = std::make_unique<J>();
+      js[i]->req = p[i];
+      js[i]->bytes = bytes[i];
+    }
     std::unique_lock<std::mutex> lk(mu_);
-    if (stop_) return INTERP_EAGAIN;
-    if (Arena::round(bytes) > arena_.size()) return INTERP_ENOMEM;
-    if ((int)queue_.size() >= max_queue_) return INTERP_EAGAIN;
-    auto j = std::make_unique<J>();
-    j->ticket = ++next_ticket_;
-    j->req = p;
-    j->bytes = bytes;
-    j->t_submit = now_ns();
-    *ticket = j->ticket;
-    queue_.push_back(j.get());
-    jobs_[j->ticket] = std::move(j);
-    ++outstanding_;
-    // When nothing runs or waits, the request is admitted and launched from
+    int rc = INTERP_OK;
+    const int64_t t = now_ns();
+    for (int i = 0; i < n; ++i) {
+      if (stop_) { rc = INTERP_EAGAIN; break; }
+      if (Arena::round(bytes[i]) > arena_.size()) { rc = INTERP_ENOMEM; break; }
+      if ((int)queue_.size() >= max_queue_) { rc = INTERP_EAGAIN; break; }
+      J* j = js[i].get();
+      j->ticket = ++next_ticket_;
+      j->t_submit = t;
+      tickets[i] = j->ticket;
+      queue_.push_back(j);
+      jobs_[j->ticket] = std::move(js[i]);
+      ++outstanding_;
+      ++*accepted;
+    }
+    // When nothing runs or waits, the requests are admitted and launched from
     // the caller's thread at once: waking the scheduler thread first would
     // cost a small request a noticeable part of its latency.  (The thread
     // is still notified: it polls the batch to completion.)
-    if (!in_round_ && queue_.size() == 1 && pending_.empty() && !any_busy()) {
+    if (*accepted > 0 && !in_round_ && queue_.size() == (size_t)*accepted && pending_.empty() &&
+        !any_busy()) {
       in_round_ = true;
       round(lk);
       in_round_ = false;
@@ -142,7 +166,7 @@ class Scheduler {
     }
     lk.unlock();
     cv_.notify_all();
-    return INTERP_OK;
+    return rc;
   }
 
   int poll(uint64_t ticket, interp_status* st) {
@@ -246,14 +270,20 @@ class Scheduler {
     }
     if (arena_.used() > peak_arena_) peak_arena_ = arena_.used();
     if (slots_used_ > peak_slots_) peak_slots_ = slots_used_;
-    // 3. launch the admitted jobs as batches on free contexts
+    // 3. launch the admitted jobs as batches on free contexts, shared evenly
+    // among them: a burst then runs as concurrent batches whose phases
+    // overlap on the device, rather than as one large batch whose every
+    // phase waits for the slowest of its jobs
     std::vector<int> go;
-    while (!pending_.empty()) {
+    size_t nfree = 0;
+    for (bool b : ctx_busy_) nfree += !b;
+    while (!pending_.empty() && nfree > 0) {
       int c = -1;
       for (size_t k = 0; k < ctx_busy_.size(); ++k)
         if (!ctx_busy_[k]) { c = (int)k; break; }
-      if (c < 0) break;
-      const size_t n = std::min(pending_.size(), (size_t)ex_->max_batch());
+      const size_t n = std::min({pending_.size(), (size_t)ex_->max_batch(),
+                                 (pending_.size() + nfree - 1) / nfree});
+      --nfree;
       ctx_jobs_[c].assign(pending_.begin(), pending_.begin() + n);
       pending_.erase(pending_.begin(), pending_.begin() + n);
       ctx_busy_[c] = true;

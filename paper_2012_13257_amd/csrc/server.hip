@@ -395,6 +395,36 @@ struct interp_server {
 
 using namespace gmm;
 
+namespace {
+// A request checked and sized for the server; "" or the reason it is invalid.
+std::string make_request(const interp_request* req, serve::Request* rq, uint64_t* bytes) {
+  rq->r = *req;
+  std::string m = make_geometry(&req->prob, &rq->g);
+  if (!m.empty()) return m;
+  if (rq->g.B != 1) return "a serving request has B = 1";
+  if (rq->g.C > serve::kServeMaxC) return "the serving path takes C <= 4";
+  if (rq->g.kern != 0) return "the serving path takes the default kernel only";
+  if (rq->g.st != INTERP_STORAGE_F32) return "the serving path takes float32 storage only";
+  if (rq->g.npass > serve::kServePasses) return "too many bins for the serving path";
+  if (rq->g.N > 0 && (!req->pos || !req->sigma || !req->values))
+    return "pos, sigma and values must not be NULL when N > 0";
+  if (!req->sigma && !rq->g.per_point && rq->g.N > 0) return "sigma must not be NULL";
+  if (!req->out) return "out must not be NULL";
+  if ((req->pos && (uintptr_t)req->pos % 8) || (req->grad_pos && (uintptr_t)req->grad_pos % 8))
+    return "pos and grad_pos must be 8-byte aligned";
+  rq->L = make_layout(rq->g);
+  *bytes = serve::Arena::round(rq->L.saved_bytes) + serve::Arena::round(rq->L.work_bytes);
+  rq->L.saved_bytes = serve::Arena::round(rq->L.saved_bytes);  // workspace starts at the next grain
+  return "";
+}
+
+int queue_result(int rc) {
+  if (rc == INTERP_ENOMEM) return fail(rc, "request can never fit the server's memory budget");
+  if (rc == INTERP_EAGAIN) return fail(rc, "server queue is full");
+  return rc;
+}
+}  // namespace
+
 extern "C" {
 
 int interp_server_create(const interp_server_config* cfg, interp_server** out) {
@@ -418,27 +448,28 @@ int interp_server_create(const interp_server_config* cfg, interp_server** out) {
 int interp_submit(interp_server* s, const interp_request* req, uint64_t* ticket) {
   if (!s || !req || !ticket) return fail(INTERP_EINVAL, "NULL argument");
   serve::Request rq;
-  rq.r = *req;
-  std::string m = make_geometry(&req->prob, &rq.g);
+  uint64_t bytes = 0;
+  const std::string m = make_request(req, &rq, &bytes);
   if (!m.empty()) return fail(INTERP_EINVAL, m);
-  if (rq.g.B != 1) return fail(INTERP_EINVAL, "a serving request has B = 1");
-  if (rq.g.C > serve::kServeMaxC) return fail(INTERP_EINVAL, "the serving path takes C <= 4");
-  if (rq.g.kern != 0) return fail(INTERP_EINVAL, "the serving path takes the default kernel only");
-  if (rq.g.st != INTERP_STORAGE_F32) return fail(INTERP_EINVAL, "the serving path takes float32 storage only");
-  if (rq.g.npass > serve::kServePasses) return fail(INTERP_EINVAL, "too many bins for the serving path");
-  if (rq.g.N > 0 && (!req->pos || !req->sigma || !req->values))
-    return fail(INTERP_EINVAL, "pos, sigma and values must not be NULL when N > 0");
-  if (!req->sigma && !rq.g.per_point && rq.g.N > 0) return fail(INTERP_EINVAL, "sigma must not be NULL");
-  if (!req->out) return fail(INTERP_EINVAL, "out must not be NULL");
-  if ((req->pos && (uintptr_t)req->pos % 8) || (req->grad_pos && (uintptr_t)req->grad_pos % 8))
-    return fail(INTERP_EINVAL, "pos and grad_pos must be 8-byte aligned");
-  rq.L = make_layout(rq.g);
-  const uint64_t bytes = serve::Arena::round(rq.L.saved_bytes) + serve::Arena::round(rq.L.work_bytes);
-  rq.L.saved_bytes = serve::Arena::round(rq.L.saved_bytes);  // workspace starts at the next grain
-  const int rc = s->sched->submit(rq, bytes, ticket);
-  if (rc == INTERP_ENOMEM) return fail(rc, "request can never fit the server's memory budget");
-  if (rc == INTERP_EAGAIN) return fail(rc, "server queue is full");
-  return rc;
+  return queue_result(s->sched->submit(rq, bytes, ticket));
+}
+
+int interp_submit_many(interp_server* s, const interp_request* reqs, int32_t n, uint64_t* tickets,
+                       int32_t* n_queued) {
+  if (!s || !n_queued || (n > 0 && (!reqs || !tickets))) return fail(INTERP_EINVAL, "NULL argument");
+  *n_queued = 0;
+  if (n < 0) return fail(INTERP_EINVAL, "n must be >= 0");
+  std::vector<serve::Request> rq(n);
+  std::vector<uint64_t> bytes(n);
+  for (int i = 0; i < n; ++i) {
+    const std::string m = make_request(&reqs[i], &rq[i], &bytes[i]);
+    if (!m.empty()) return fail(INTERP_EINVAL, "request " + std::to_string(i) + ": " + m);
+  }
+  if (n == 0) return INTERP_OK;
+  int queued = 0;
+  const int rc = s->sched->submit_many(rq.data(), bytes.data(), n, tickets, &queued);
+  *n_queued = queued;
+  return queue_result(rc);
 }
 
 int interp_poll(interp_server* s, uint64_t ticket, interp_status* status) {

@@ -5,6 +5,7 @@
     t = srv.submit(pos, sigma, values, H, W, grad_out=G) # forward + backward
     ...
     res = srv.result(t)   # None while queued/running; dict when done
+    ts = srv.submit_many([srv.prepare(pos, sigma, values, H, W), ...])  # one call, many requests
 
 Every request is one image (B = 1) with C <= 4 channels.  When torch's
 current stream still has work queued, submit records an event on it after
@@ -18,7 +19,7 @@ been collected.
 from __future__ import annotations
 
 import ctypes
-from typing import Dict, Optional
+from typing import Dict, List, Optional
 
 import torch
 
@@ -47,14 +48,13 @@ class Server:
         e.record(torch.cuda.current_stream(self._device))  # creates the HIP event now
         return e
 
-    def submit(self, pos, sigma, values, H: int, W: int, radius: float = 3.0, tile: int = 8,
-               grad_out: Optional[torch.Tensor] = None, grads=("pos", "sigma", "values"),
-               out: Optional[torch.Tensor] = None, grad_buffers: Optional[dict] = None,
-               after_stream: bool = True) -> int:
-        """Queues one request.  out / grad_buffers ({"pos": t, "sigma": t,
-        "values": t}) may supply preallocated result tensors.  after_stream:
-        order the request after the work queued so far on torch's current
-        stream (False: the caller guarantees its inputs and buffers are ready)."""
+    def prepare(self, pos, sigma, values, H: int, W: int, radius: float = 3.0, tile: int = 8,
+                grad_out: Optional[torch.Tensor] = None, grads=("pos", "sigma", "values"),
+                out: Optional[torch.Tensor] = None,
+                grad_buffers: Optional[dict] = None) -> "Prepared":
+        """A request described for submission (submit_many), its result tensors
+        allocated.  out / grad_buffers ({"pos": t, "sigma": t, "values": t}) may
+        supply preallocated result tensors."""
         prob = problem(pos, sigma, values, H, W, radius, tile)
         if out is None:
             out = torch.empty((1, prob.C, prob.H, prob.W), dtype=torch.float32, device=self._device)
@@ -80,21 +80,66 @@ class Server:
             if "values" in grads:
                 keep["grad_values"] = gb["values"] if "values" in gb else torch.empty_like(values)
                 req.grad_values = keep["grad_values"].data_ptr()
+        return Prepared(req, keep)
+
+    def _ready_event(self, after_stream: bool):
+        """An event recorded on torch's current stream when it still has work
+        queued, else None.  (An event recorded on an idle stream would be one
+        more marker on a hardware queue that the runtime may share with a
+        server stream, which would then order the request behind another
+        batch.)"""
         stream = torch.cuda.current_stream(self._device)
-        # An idle stream needs no event: its work is done.  (An event recorded
-        # on it would be one more marker on a hardware queue that the
-        # runtime may share with a server stream, which would then order the
-        # request behind another batch.)
-        if after_stream and not stream.query():
-            ready = self._events.pop() if self._events else self._new_event()
-            ready.record(stream)
-            keep["ready"] = ready
-            req.ready = ready.cuda_event
+        if not after_stream or stream.query():
+            return None
+        ready = self._events.pop() if self._events else self._new_event()
+        ready.record(stream)
+        return ready
+
+    def submit(self, pos, sigma, values, H: int, W: int, radius: float = 3.0, tile: int = 8,
+               grad_out: Optional[torch.Tensor] = None, grads=("pos", "sigma", "values"),
+               out: Optional[torch.Tensor] = None, grad_buffers: Optional[dict] = None,
+               after_stream: bool = True) -> int:
+        """Queues one request (arguments as for prepare).  after_stream: order
+        the request after the work queued so far on torch's current stream
+        (False: the caller guarantees its inputs and buffers are ready)."""
+        pr = self.prepare(pos, sigma, values, H, W, radius, tile, grad_out, grads, out, grad_buffers)
+        ready = self._ready_event(after_stream)
+        if ready is not None:
+            pr.keep["ready"] = ready
+            pr.req.ready = ready.cuda_event
         ticket = ctypes.c_uint64()
-        _lib.check("interp_submit", _lib.lib().interp_submit(self._h, ctypes.byref(req),
+        _lib.check("interp_submit", _lib.lib().interp_submit(self._h, ctypes.byref(pr.req),
                                                              ctypes.byref(ticket)))
-        self._live[ticket.value] = keep
+        self._live[ticket.value] = pr.keep
         return ticket.value
+
+    def submit_many(self, prepared, after_stream: bool = True) -> List[int]:
+        """Queues prepared requests (a list of prepare()'s results, or a Batch
+        of them) in one call and returns their tickets in order.  One event on
+        torch's current stream orders them all (see submit).  If the server
+        cannot queue them all, the InterpError raised carries the tickets of
+        those it queued (attribute tickets); the others were not queued."""
+        batch = prepared if isinstance(prepared, Batch) else Batch(prepared)
+        n = len(batch.items)
+        ready = self._ready_event(after_stream)
+        if ready is not None:
+            for i in range(n):
+                batch.array[i].ready = ready.cuda_event
+        tickets = (ctypes.c_uint64 * max(n, 1))()
+        queued = ctypes.c_int32()
+        rc = _lib.lib().interp_submit_many(self._h, batch.array, n, tickets, ctypes.byref(queued))
+        out = []
+        for i in range(queued.value):
+            keep = dict(batch.items[i].keep)
+            if ready is not None:
+                keep["ready_shared"] = ready  # kept alive, not returned to the pool
+            self._live[tickets[i]] = keep
+            out.append(tickets[i])
+        if rc != _lib.INTERP_OK:
+            err = _lib.InterpError("interp_submit_many", rc, _lib.last_error())
+            err.tickets = out
+            raise err
+        return out
 
     def poll(self, ticket: int) -> _lib.Status:
         st = _lib.Status()
@@ -140,3 +185,22 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+class Prepared:
+    """One request described for the C ABI (interp_request) and the tensors it
+    uses, which must stay alive until its result is collected."""
+    __slots__ = ("req", "keep")
+
+    def __init__(self, req, keep: dict):
+        self.req = req
+        self.keep = keep
+
+
+class Batch:
+    """Prepared requests laid out as the array interp_submit_many reads;
+    building it once ahead keeps the copy out of the submitting call."""
+
+    def __init__(self, prepared):
+        self.items = list(prepared)
+        self.array = (_lib.Request * max(len(self.items), 1))(*[p.req for p in self.items])

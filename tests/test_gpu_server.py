@@ -76,6 +76,57 @@ def test_server_results_equal_single_call_alone_and_in_mix():
         assert nb > 0
 
 
+def test_server_submit_many_equals_single_call_and_checks_every_request():
+    """interp_submit_many: one call queues a mix of requests in order; each
+    result equals the single-call path bitwise.  A batch with one invalid
+    request queues nothing; a batch that overflows the queue queues a
+    prefix, whose results are still right."""
+    import torch
+    from paper_2012_13257_amd import _lib
+    from paper_2012_13257_amd.server import Batch, Server
+    reqs = _requests(40, 8765)
+    dev = [_dev(wl) for _, wl in reqs]
+    torch.cuda.synchronize()
+    ref = [_single(p, s, v, G, wl, r.backward) for (r, wl), (p, s, v, G) in zip(reqs, dev)]
+    torch.cuda.synchronize()
+    with Server(budget_bytes=2 << 30, max_slots=16) as srv:
+        say("server submit_many")
+        prep = [srv.prepare(p, s, v, wl.H, wl.W, wl.radius, grad_out=G if r.backward else None)
+                for (r, wl), (p, s, v, G) in zip(reqs, dev)]
+        tickets = srv.submit_many(Batch(prep))
+        assert len(tickets) == len(reqs) and tickets == sorted(tickets)
+        assert srv.drain(120000)
+        for k, t in enumerate(tickets):
+            res = srv.result(t)
+            assert res is not None and res["state"] == 2, (k, res)
+            for key, val in ref[k].items():
+                assert torch.equal(res[key], val), (k, key)
+        # one invalid request (five channels) in the middle: nothing is queued
+        p5 = torch.rand((1, 10, 2), device="cuda") * 16
+        v5 = torch.rand((1, 10, 5), device="cuda")
+        s5 = torch.full((1,), 1.0, device="cuda")
+        bad = srv.prepare(p5, s5, v5, 16, 16)
+        (r0, wl0), (p0, s0, v0, _) = reqs[0], dev[0]
+        good = srv.prepare(p0, s0, v0, wl0.H, wl0.W, wl0.radius)
+        with pytest.raises(_lib.InterpError) as ei:
+            srv.submit_many([good, bad, good])
+        assert ei.value.code == _lib.INTERP_EINVAL and ei.value.tickets == []
+        assert "request 1" in str(ei.value)
+    # a queue of three: the first three of five are queued and run
+    with Server(budget_bytes=2 << 30, max_slots=2, max_queue=3) as srv:
+        say("server submit_many, queue limit")
+        prep = [srv.prepare(p, s, v, wl.H, wl.W, wl.radius) for (r, wl), (p, s, v, G) in
+                zip(reqs[:5], dev[:5])]
+        with pytest.raises(_lib.InterpError) as ei:
+            srv.submit_many(prep)
+        assert ei.value.code == _lib.INTERP_EAGAIN and len(ei.value.tickets) == 3
+        assert srv.drain(60000)
+        for k, t in enumerate(ei.value.tickets):
+            res = srv.result(t)
+            assert res["state"] == 2
+            assert torch.equal(res["out"], ref[k]["out"]), k
+
+
 def test_server_matches_oracle_on_small_requests():
     """Forward of every request and, for the requests that ask for it, every
     gradient, against the oracle (the server exports no Z: empty pixels are

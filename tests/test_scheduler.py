@@ -30,6 +30,9 @@ def L():
                                     ctypes.c_int]
     lib.gmm_fake_submit.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int,
                                     ctypes.POINTER(ctypes.c_uint64)]
+    lib.gmm_fake_submit_many.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int,
+                                         ctypes.c_int64, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64),
+                                         ctypes.POINTER(ctypes.c_int)]
     lib.gmm_fake_poll.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(Status)]
     lib.gmm_fake_drain.argtypes = [ctypes.c_void_p, ctypes.c_int64]
     lib.gmm_fake_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]
@@ -49,6 +52,14 @@ class Fake:
         t = ctypes.c_uint64()
         rc = self.L.gmm_fake_submit(self.h, nbytes, delay_us, fail, ctypes.byref(t))
         return rc, t.value
+
+    def submit_many(self, sizes, delay_us=0, fail=0):
+        n = len(sizes)
+        b = (ctypes.c_uint64 * max(n, 1))(*sizes)
+        t = (ctypes.c_uint64 * max(n, 1))()
+        acc = ctypes.c_int(-1)
+        rc = self.L.gmm_fake_submit_many(self.h, b, n, delay_us, fail, t, ctypes.byref(acc))
+        return rc, list(t)[:acc.value]
 
     def poll(self, t):
         s = Status()
@@ -185,5 +196,41 @@ def test_destroy_with_pending_fails_queued_and_finishes_running(L):
         assert states[0].state == DONE
         assert all(s.state == FAILED and s.err == EAGAIN for s in states[1:])
         assert f.submit(1000)[0] == EAGAIN   # a stopped server takes nothing
+    finally:
+        f.close()
+
+
+def test_submit_many_queues_in_order_and_completes(L):
+    f = Fake(L, budget=1 << 20, slots=1, queue=100, contexts=1, max_batch=1)
+    try:
+        rc, ts = f.submit_many([1000] * 12, delay_us=300)
+        assert rc == OK and len(ts) == 12
+        assert ts == sorted(ts) and len(set(ts)) == 12
+        assert f.drain(10000) == OK
+        st = [f.poll(t)[1] for t in ts]
+        assert all(s.state == DONE for s in st)
+        # one submit time for the call; admission in array order
+        assert len({s.t_submit_ns for s in st}) == 1
+        admits = [s.t_admit_ns for s in st]
+        assert admits == sorted(admits)
+        assert f.submit_many([]) == (OK, [])
+    finally:
+        f.close()
+
+
+def test_submit_many_stops_at_the_first_request_it_cannot_queue(L):
+    f = Fake(L, budget=1 << 16, slots=1, queue=4, contexts=1, max_batch=1)
+    try:
+        # the third can never fit the budget: the first two are queued
+        rc, ts = f.submit_many([1000, 1000, (1 << 16) + 1, 1000], delay_us=100)
+        assert rc == ENOMEM and len(ts) == 2
+        assert f.drain(10000) == OK
+        assert all(f.poll(t)[1].state == DONE for t in ts)
+        # queue of four: the fifth and later are refused, the rest run
+        rc, ts = f.submit_many([1000] * 7, delay_us=20000)
+        assert rc == EAGAIN and len(ts) == 4
+        assert f.drain(20000) == OK
+        assert all(f.poll(t)[1].state == DONE for t in ts)
+        assert f.stats()["overlaps"] == 0
     finally:
         f.close()
