@@ -348,6 +348,25 @@ class GpuExecutor {
       e = hipStreamWaitEvent(x.stream, ev, 0);
       if (e != hipSuccess) return fail_hip(e, "hipStreamWaitEvent(ready)");
     }
+    if (nj == 1) {
+      // A batch of one request runs the single-call kernels on the context's
+      // stream: the same results bit for bit, without the table upload and
+      // the graph launch (which cost a lone small request a good part of
+      // its latency).
+      const Request& rq = jobs[0]->req;
+      char* base = static_cast<char*>(arena_) + jobs[0]->arena_off;
+      char* work = base + rq.L.saved_bytes;
+      const ImageView& v0 = T->view[0];
+      e = launch_forward_all(rq.g, v0, reinterpret_cast<int*>(work + rq.L.fplan), x.stream);
+      if (e != hipSuccess) return fail_hip(e, "forward kernels");
+      if (need_bwd) {
+        e = launch_backward_all(rq.g, v0, x.stream);
+        if (e != hipSuccess) return fail_hip(e, "backward kernels");
+      }
+      e = hipEventRecord(x.done, x.stream);
+      if (e != hipSuccess) return fail_hip(e, "hipEventRecord");
+      return INTERP_OK;
+    }
     const size_t bytes = offsetof(JobTable, view) + sizeof(ImageView) * (size_t)nj;
     e = hipMemcpyAsync(x.dtab, T, bytes, hipMemcpyHostToDevice, x.stream);
     if (e != hipSuccess) return fail_hip(e, "hipMemcpyAsync(table)");

@@ -122,9 +122,12 @@ class Server:
         batch = prepared if isinstance(prepared, Batch) else Batch(prepared)
         n = len(batch.items)
         ready = self._ready_event(after_stream)
-        if ready is not None:
+        if ready is not None or batch.has_ready:
+            # (a batch submitted again must not keep an earlier call's event)
+            ev = ready.cuda_event if ready is not None else None
             for i in range(n):
-                batch.array[i].ready = ready.cuda_event
+                batch.array[i].ready = ev
+            batch.has_ready = ready is not None
         tickets = (ctypes.c_uint64 * max(n, 1))()
         queued = ctypes.c_int32()
         rc = _lib.lib().interp_submit_many(self._h, batch.array, n, tickets, ctypes.byref(queued))
@@ -204,3 +207,4 @@ class Batch:
     def __init__(self, prepared):
         self.items = list(prepared)
         self.array = (_lib.Request * max(len(self.items), 1))(*[p.req for p in self.items])
+        self.has_ready = any(p.req.ready for p in self.items)

@@ -191,6 +191,28 @@ def test_server_waits_for_the_callers_stream():
         res = srv.result(t)
         assert res["state"] == 2
         assert torch.equal(res["out"], ref["out"])
+        # the same through submit_many, one batch submitted twice: behind a
+        # busy stream (one shared event), then with the stream idle
+        say("server submit_many ordered after the caller's stream")
+        from paper_2012_13257_amd.server import Batch
+        v3 = torch.zeros_like(v)
+        batch = Batch([srv.prepare(p, s, v3, wl.H, wl.W, wl.radius) for _ in range(3)])
+        for _ in range(8):
+            junk = junk @ junk
+            junk = junk / junk.norm()
+        v3.copy_(v + 0.0 * junk[0, 0])
+        ts = srv.submit_many(batch)
+        assert srv.drain(60000)
+        for t in ts:
+            res = srv.result(t)
+            assert res["state"] == 2 and torch.equal(res["out"], ref["out"])
+        torch.cuda.synchronize()
+        ts = srv.submit_many(batch)
+        assert not batch.has_ready and all(batch.array[i].ready is None for i in range(3))
+        assert srv.drain(60000)
+        for t in ts:
+            res = srv.result(t)
+            assert res["state"] == 2 and torch.equal(res["out"], ref["out"])
 
 
 def test_server_budget_and_argument_errors():
