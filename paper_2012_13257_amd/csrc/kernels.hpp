@@ -68,6 +68,22 @@ __device__ inline float4 make_geo(float2 p, float2 sg, float radius, bool diag) 
   return make_float4(p.x, p.y, kk, R2);
 }
 
+// The point's sigma (sigma_x, sigma_y) recovered from its sorted record, for
+// the adjoint's disk extent and chain rule: reading sigma at the point's
+// original index would be a gather with a dependent address.  Isotropic:
+// sigma^2 = -log2(e) / (2 k); diagonal: sigma = 1 / (1/sigma).  Within a few
+// float32 roundings of the input sigma, which moves the gradients' scale
+// factors by a few parts in 1e7 and stays far inside the extents' margins.
+template <bool kDiag>
+__device__ inline float2 record_sigma(float4 g) {
+  if constexpr (kDiag) {
+    return make_float2(1.0f / g.z, 1.0f / g.w);
+  } else {
+    const float s = __builtin_sqrtf(-0.5f * kLog2e / g.z);
+    return make_float2(s, s);
+  }
+}
+
 // The normal density's factor 1/(2 pi sigma_x sigma_y) of a normalised
 // kernel, from the point's record: the isotropic record holds
 // k = -log2(e) / (2 sigma^2), so the factor is k * (-1 / (pi log2(e)));
@@ -1138,7 +1154,7 @@ __device__ inline void bwd_point(const ImageView& v, int unit, float* red4, int*
     for (int k = 0; k < CT; ++k) cc[k] = Val<ST>::load(v.col, (size_t)t * CS + k);
     const float zeta = kN ? record_density<kD>(g) : 1.0f;
     const int j = v.perm[t];
-    const float2 sg = sigma2_of(v, j);
+    const float2 sg = record_sigma<kD>(g);
     const float Rhx = conservative_reach(__fmul_rn(v.radius, sg.x));
     const float Rh = conservative_reach(__fmul_rn(v.radius, sg.y));  // along y
     // bounding box of the disk (ellipse), clipped to the image (the float
@@ -1381,7 +1397,7 @@ __device__ inline void bwd_point_wide(const ImageView& v, int unit, float* red4,
     }
     const float zeta = kN ? record_density<kD>(g) : 1.0f;
     const int j = v.perm[t];
-    const float2 sg = sigma2_of(v, j);
+    const float2 sg = record_sigma<kD>(g);
     const float Rh = conservative_reach(__fmul_rn(v.radius, sg.y));  // along y
     const float fvlo = fminf(fmaxf(ceilf(g.y - Rh), 0.0f), (float)v.H);
     const float fvhi = fmaxf(fminf(floorf(g.y + Rh), (float)(v.H - 1)), -1.0f);
