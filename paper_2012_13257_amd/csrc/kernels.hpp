@@ -1019,10 +1019,12 @@ __device__ inline void forward_block_q(const ImageView& v, int unit, int mode, f
 // Backward
 // ---------------------------------------------------------------------------
 
-// unit = 256 pixels: G'_ik = G_ik / Z_i and beta_i = sum_k G_ik out_ik / Z_i,
-// packed per pixel as (G'_0 .. G'_{CT-1}, beta, zero padding).  Interleaved
-// ([H*W][CP]) for the one-lane-per-point adjoint; planar ([CP/4][H*W] groups
-// of four values) for the eight-lanes-per-point adjoint of many channels.
+// unit = 256 pixels: G'_ik = G_ik / Z_i and beta_i = sum_k G_ik out_ik / Z_i.
+// Interleaved ([H*W][CP]: G'_0 .. G'_{CT-1}, beta, zero padding) for the
+// one-lane-per-point adjoint; planar for the eight-lanes-per-point adjoint of
+// many channels (CT a multiple of four): [CT/4][H*W] groups of four G' values,
+// then [H*W] betas (a plane of its own, so that reading beta costs 4 bytes,
+// not a padded group of 16).
 template <int CT, int ST = INTERP_STORAGE_F32, bool kPlanar = false>
 __device__ inline void bwd_pixel(const ImageView& v, int unit) {
   constexpr int CP = (CT + 1 + 3) / 4 * 4;
@@ -1048,10 +1050,12 @@ __device__ inline void bwd_pixel(const ImageView& v, int unit) {
     rec[CT] = beta * a;
   }
   if constexpr (kPlanar) {
+    static_assert(CT % 4 == 0, "planar records: whole groups of four values");
     float4* dst = reinterpret_cast<float4*>(v.prec) + i;
 #pragma unroll
-    for (int q = 0; q < CP / 4; ++q)
+    for (int q = 0; q < CT / 4; ++q)
       dst[(size_t)q * HW] = make_float4(rec[4 * q], rec[4 * q + 1], rec[4 * q + 2], rec[4 * q + 3]);
+    reinterpret_cast<float*>(reinterpret_cast<float4*>(v.prec) + (size_t)(CT / 4) * HW)[i] = rec[CT];
   } else {
     float4* dst = reinterpret_cast<float4*>(v.prec + (size_t)i * CP);
 #pragma unroll
@@ -1355,8 +1359,6 @@ __device__ inline void bwd_point_wide(const ImageView& v, int unit, float* red4,
   constexpr int CS = CT;
   constexpr bool kD = kDiagonal<KV>, kN = kNormalized<KV>;
   constexpr int NC = CT;
-  constexpr int CP = (NC + 1 + 3) / 4 * 4;
-  constexpr int CP4 = CP / 4;
   const int base = unit * 256;
   // within each round of 32 consecutive points, the points in order of disk
   // size (class of half a pixel of extent, ties by position), so that the
@@ -1384,6 +1386,7 @@ __device__ inline void bwd_point_wide(const ImageView& v, int unit, float* red4,
   const int grp = lane >> 3, l = lane & 7;
   const size_t HW = (size_t)v.H * v.W;
   const float4* prec4 = reinterpret_cast<const float4*>(v.prec);
+  const float* betap = reinterpret_cast<const float*>(prec4 + (size_t)(NC / 4) * HW);
   for (int r = 0; r < 8; ++r) {
     const int lp = order[r * 32 + wid * 8 + grp];
     const int t = base + lp;
@@ -1424,12 +1427,13 @@ __device__ inline void bwd_point_wide(const ImageView& v, int unit, float* red4,
     // px inside the chord; w = 0 when px is not)
     auto pixel = [&](int py, int px, bool inside, int pxc, float dyy, float qy) {
       const float4* rowp = prec4 + (size_t)py * v.W;
-      float rec[CP];
+      float rec[NC + 1];
 #pragma unroll
-      for (int q = 0; q < CP4; ++q) {
+      for (int q = 0; q < NC / 4; ++q) {
         const float4 r4 = rowp[(size_t)q * HW + pxc];
         rec[4 * q] = r4.x; rec[4 * q + 1] = r4.y; rec[4 * q + 2] = r4.z; rec[4 * q + 3] = r4.w;
       }
+      rec[NC] = betap[(size_t)py * v.W + pxc];
       const float dx = (float)px - g.x;
       const float qx = kD ? dx * g.z : dx;
       const float qxx = qx * qx;
