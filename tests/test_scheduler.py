@@ -234,3 +234,19 @@ def test_submit_many_stops_at_the_first_request_it_cannot_queue(L):
         assert f.stats()["overlaps"] == 0
     finally:
         f.close()
+
+
+def test_admitted_jobs_are_shared_among_free_contexts(L):
+    """A burst queued at once runs as concurrent batches of equal size, not
+    as one large batch on one context."""
+    f = Fake(L, budget=1 << 24, slots=64, queue=1000, contexts=4, max_batch=64)
+    try:
+        rc, ts = f.submit_many([1000] * 64, delay_us=20000)
+        assert rc == OK and len(ts) == 64
+        assert f.drain(20000) == OK
+        st = f.stats()
+        assert st["peak_ctx"] == 4
+        assert st["max_batch"] == 16
+        assert st["batches"] == 4
+    finally:
+        f.close()
