@@ -533,19 +533,20 @@ def serving_benchmark(log, n_requests: int = 4096, seed: int = 1004, budget_gb: 
         return done, done - arrivals
 
     def server_run(arrivals, many=False):
-        """many: every request (all arriving at once) prepared ahead and queued
-        by one interp_submit_many call, so the Python submit loop does not
-        pace the server."""
+        """Every request is described ahead (Server.prepare: the descriptor and
+        its buffers, as the baseline's are), so the timed loop pays only the
+        submission.  many: all of them (all arriving at once) queued by one
+        interp_submit_many call, so the Python submit loop does not pace the
+        server."""
         srv = Server(budget_bytes=int(budget_gb * (1 << 30)), max_slots=slots)
         try:
             tickets = []
-            batch = None
-            if many:
-                batch = Batch([srv.prepare(q["pos"], q["sig"], q["val"], q["r"].side, q["r"].side,
-                                           3.0, grad_out=q["G"], out=q["out"],
-                                           grad_buffers=None if q["grads"] is None else
-                                           dict(zip(("pos", "sigma", "values"), q["grads"])))
-                               for q in reqs])
+            prepared = [srv.prepare(q["pos"], q["sig"], q["val"], q["r"].side, q["r"].side, 3.0,
+                                    grad_out=q["G"], out=q["out"],
+                                    grad_buffers=None if q["grads"] is None else
+                                    dict(zip(("pos", "sigma", "values"), q["grads"])))
+                        for q in reqs]
+            batch = Batch(prepared) if many else None
             torch.cuda.synchronize()
             gc.collect()
             gc.disable()
@@ -554,15 +555,10 @@ def serving_benchmark(log, n_requests: int = 4096, seed: int = 1004, budget_gb: 
                 if many:
                     tickets = srv.submit_many(batch)
                 else:
-                    for q, a in zip(reqs, arrivals):
+                    for pr, a in zip(prepared, arrivals):
                         while time.monotonic_ns() - t0 < a * 1e9:
                             pass
-                        gb = None
-                        if q["grads"] is not None:
-                            gb = dict(zip(("pos", "sigma", "values"), q["grads"]))
-                        tickets.append(srv.submit(q["pos"], q["sig"], q["val"], q["r"].side,
-                                                  q["r"].side, 3.0, grad_out=q["G"], out=q["out"],
-                                                  grad_buffers=gb))
+                        tickets.append(srv.submit_prepared(pr))
                 srv.drain()
             finally:
                 gc.enable()

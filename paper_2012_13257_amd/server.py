@@ -103,14 +103,20 @@ class Server:
         the request after the work queued so far on torch's current stream
         (False: the caller guarantees its inputs and buffers are ready)."""
         pr = self.prepare(pos, sigma, values, H, W, radius, tile, grad_out, grads, out, grad_buffers)
+        return self.submit_prepared(pr, after_stream)
+
+    def submit_prepared(self, pr: "Prepared", after_stream: bool = True) -> int:
+        """Queues one request prepare() described (a client can describe its
+        requests ahead and pay only this call when they arrive); as submit."""
         ready = self._ready_event(after_stream)
-        if ready is not None:
-            pr.keep["ready"] = ready
-            pr.req.ready = ready.cuda_event
+        pr.req.ready = ready.cuda_event if ready is not None else None
         ticket = ctypes.c_uint64()
         _lib.check("interp_submit", _lib.lib().interp_submit(self._h, ctypes.byref(pr.req),
                                                              ctypes.byref(ticket)))
-        self._live[ticket.value] = pr.keep
+        keep = pr.keep
+        if ready is not None:
+            keep = dict(keep, ready=ready)
+        self._live[ticket.value] = keep
         return ticket.value
 
     def submit_many(self, prepared, after_stream: bool = True) -> List[int]:
