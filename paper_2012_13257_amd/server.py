@@ -5,6 +5,8 @@
     t = srv.submit(pos, sigma, values, H, W, grad_out=G) # forward + backward
     ...
     res = srv.result(t)   # None while queued/running; dict when done
+    pr = srv.prepare(pos, sigma, values, H, W)          # described ahead ...
+    t = srv.submit_prepared(pr)                          # ... submitted when it arrives
     ts = srv.submit_many([srv.prepare(pos, sigma, values, H, W), ...])  # one call, many requests
 
 Every request is one image (B = 1) with C <= 4 channels.  When torch's
