@@ -101,6 +101,14 @@ def test_server_submit_many_equals_single_call_and_checks_every_request():
             assert res is not None and res["state"] == 2, (k, res)
             for key, val in ref[k].items():
                 assert torch.equal(res[key], val), (k, key)
+        # a prepared request submitted again on its own gives the same bits
+        for k in (0, 7):
+            t = srv.submit_prepared(prep[k])
+            assert srv.drain(60000)
+            res = srv.result(t)
+            assert res["state"] == 2
+            for key, val in ref[k].items():
+                assert torch.equal(res[key], val), (k, key)
         # one invalid request (five channels) in the middle: nothing is queued
         p5 = torch.rand((1, 10, 2), device="cuda") * 16
         v5 = torch.rand((1, 10, 5), device="cuda")
